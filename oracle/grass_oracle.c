@@ -1,0 +1,650 @@
+/*
+ * GRASS oracle: a plain, slow, single-threaded FP64 CPU implementation of the
+ * spectral off-tree edge embedding, filtering and iterative densification of
+ * Feng, "GRASS: Graph Spectral Sparsification Leveraging Scalable Spectral
+ * Perturbation Analysis" (arXiv:1911.04382).
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product library calls, links or
+ * loads this file; only the test-suite, the smoke check and the CPU baseline
+ * of the benchmark do. It shares no code, header, table or helper with the GPU
+ * path. Every sum runs in ascending edge-id or node order.
+ *
+ * Equation numbers are those of the paper, in its LaTeX numbering (1)-(61);
+ * sections are Sec. II (background), III (perturbation analysis), IV
+ * (similarity-aware filtering), V (experiments).
+ *
+ * Readings taken where the paper is silent (each is repeated at its function):
+ *  - spanning tree: maximum weight, ties broken by the smaller edge id, so the
+ *    tree is unique (the paper suggests a low-stretch tree, Sec. III-A/III-I);
+ *  - grounding: x[root] = 0 exactly, root = node 0 (Sec. III-F adds a tiny
+ *    diagonal term to one row instead; for right-hand sides orthogonal to the
+ *    all-ones vector the two agree up to a constant shift, which every heat
+ *    value ignores);
+ *  - random vectors: Philox4x64-10 Gaussians, mean removed per vector (eq. 28);
+ *  - lambda_max estimate: Rayleigh quotient h'L_G h / h'L_P h of the t-step
+ *    vectors, maximum over vectors (Sec. IV-C.1);
+ *  - similarity check: topological greedy (Sec. IV-D step 6 gives no measure);
+ *  - per-pass edge budget floor(budget_frac * n) ("a small portion", Sec. III-I
+ *    step 5 and Sec. IV-D).
+ * Parity unpinned by the paper: the similarity check, the per-pass budget, the
+ * PCG tolerance and the lambda_max step count (they are fixed only by the
+ * readings above).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "grass_oracle.h"
+
+/* ===================================================== validation (Sec. II-A) */
+
+static int64_t uf_find(int64_t *p, int64_t x) {
+    while (p[x] != x) {
+        p[x] = p[p[x]];
+        x = p[x];
+    }
+    return x;
+}
+
+/* G must be weighted, undirected and connected with positive weights (Sec. II-A,
+ * Sec. III-A). The edge list must be canonical: src < dst, sorted by (src, dst),
+ * no duplicates. Returns ORC_OK, ORC_ERR_INVALID or ORC_ERR_DISCONNECTED. */
+int orc_validate(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w) {
+    if (n < 2 || m < 1) return ORC_ERR_INVALID;
+    for (int64_t e = 0; e < m; e++) {
+        if (src[e] < 0 || dst[e] >= n || src[e] >= dst[e]) return ORC_ERR_INVALID;
+        if (!(w[e] > 0.0) || !isfinite(w[e])) return ORC_ERR_INVALID;
+        if (e > 0) {
+            if (src[e] < src[e - 1] || (src[e] == src[e - 1] && dst[e] <= dst[e - 1])) return ORC_ERR_INVALID;
+        }
+    }
+    int64_t *par = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t v = 0; v < n; v++) par[v] = v;
+    int64_t comps = n;
+    for (int64_t e = 0; e < m; e++) {
+        int64_t a = uf_find(par, src[e]), b = uf_find(par, dst[e]);
+        if (a != b) {
+            par[a] = b;
+            comps--;
+        }
+    }
+    free(par);
+    return comps == 1 ? ORC_OK : ORC_ERR_DISCONNECTED;
+}
+
+/* ============================================ spanning tree (Sec. III-I step 1) */
+
+static const double *g_sort_w; /* qsort context (single-threaded oracle) */
+static int cmp_desc_w_asc_id(const void *a, const void *b) {
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    double wx = g_sort_w[x], wy = g_sort_w[y];
+    if (wx > wy) return -1;
+    if (wx < wy) return 1;
+    return (x > y) - (x < y);
+}
+
+/* Kruskal: scan edges by (weight descending, id ascending) and keep every edge
+ * joining two different components. Writes mask[e] = 1 for tree edges, 0
+ * otherwise; returns the number of tree edges (n - 1 when connected). */
+int64_t orc_max_spanning_tree(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                              uint8_t *mask) {
+    int64_t *ord = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+    for (int64_t e = 0; e < m; e++) ord[e] = e;
+    g_sort_w = w;
+    qsort(ord, (size_t)m, sizeof(int64_t), cmp_desc_w_asc_id);
+    int64_t *par = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t v = 0; v < n; v++) par[v] = v;
+    memset(mask, 0, (size_t)m);
+    int64_t cnt = 0;
+    for (int64_t i = 0; i < m; i++) {
+        int64_t e = ord[i];
+        int64_t a = uf_find(par, src[e]), b = uf_find(par, dst[e]);
+        if (a != b) {
+            par[a] = b;
+            mask[e] = 1;
+            cnt++;
+        }
+    }
+    free(par);
+    free(ord);
+    return cnt;
+}
+
+/* ==================================================== Laplacian (eqs. 1, 2) */
+
+/* y = L x for the graph made of the edges with use[e] != 0 (all edges when use
+ * is NULL). x, y are n x k, row-major (k values per node). Edge form of eq. (1):
+ * every edge (p, q, w) adds w (x_p - x_q) to y_p and w (x_q - x_p) to y_q. */
+void orc_laplacian_apply(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                         const uint8_t *use, int k, const double *x, double *y) {
+    memset(y, 0, (size_t)n * (size_t)k * sizeof(double));
+    for (int64_t e = 0; e < m; e++) {
+        if (use && !use[e]) continue;
+        const double *xp = x + (size_t)src[e] * k, *xq = x + (size_t)dst[e] * k;
+        double *yp = y + (size_t)src[e] * k, *yq = y + (size_t)dst[e] * k;
+        for (int j = 0; j < k; j++) {
+            double d = w[e] * (xp[j] - xq[j]);
+            yp[j] += d;
+            yq[j] -= d;
+        }
+    }
+}
+
+/* Weighted degrees (the diagonal of eq. (1)) of the edges with use[e] != 0. */
+void orc_weighted_degree(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                         const uint8_t *use, double *deg) {
+    memset(deg, 0, (size_t)n * sizeof(double));
+    for (int64_t e = 0; e < m; e++) {
+        if (use && !use[e]) continue;
+        deg[src[e]] += w[e];
+        deg[dst[e]] += w[e];
+    }
+}
+
+/* ===================================================== rooted tree, tree solve */
+
+/* Orient the tree made of the edges with tree[e] == 1 from `root` by breadth-first
+ * search. parent[root] = -1; pw[v] = weight of the edge (v, parent[v]); order[]
+ * lists the nodes in BFS order (root first). Returns 0, or -1 if those edges do
+ * not form a spanning tree. */
+int orc_root_tree(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                  const uint8_t *tree, int64_t root, int64_t *parent, double *pw, int64_t *order) {
+    int64_t *deg = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t cnt = 0;
+    for (int64_t e = 0; e < m; e++)
+        if (tree[e] == 1) {
+            deg[src[e] + 1]++;
+            deg[dst[e] + 1]++;
+            cnt++;
+        }
+    if (cnt != n - 1) {
+        free(deg);
+        return -1;
+    }
+    for (int64_t v = 0; v < n; v++) deg[v + 1] += deg[v];
+    int64_t *adj = (int64_t *)malloc((size_t)(2 * cnt + 1) * sizeof(int64_t));
+    int64_t *fill = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    for (int64_t v = 0; v < n; v++) fill[v] = deg[v];
+    for (int64_t e = 0; e < m; e++)
+        if (tree[e] == 1) {
+            adj[fill[src[e]]++] = e;
+            adj[fill[dst[e]]++] = e;
+        }
+    for (int64_t v = 0; v < n; v++) parent[v] = -2;
+    parent[root] = -1;
+    pw[root] = 0.0;
+    int64_t head = 0, tail = 0;
+    order[tail++] = root;
+    while (head < tail) {
+        int64_t u = order[head++];
+        for (int64_t i = deg[u]; i < deg[u + 1]; i++) {
+            int64_t e = adj[i];
+            int64_t v = src[e] == u ? dst[e] : src[e];
+            if (parent[v] != -2) continue;
+            parent[v] = u;
+            pw[v] = w[e];
+            order[tail++] = v;
+        }
+    }
+    free(adj);
+    free(fill);
+    free(deg);
+    return tail == n ? 0 : -1;
+}
+
+/* Grounded tree solve: x with x[root] = 0 and (L_T x)_v = b_v for every v != root
+ * (b[root] is ignored). Sequential elimination of the tree Laplacian, the linear
+ * time tree factorisation of Sec. III-I:
+ *   up:   f = b; leaves to root: f[parent v] += f[v]   (f[v] = current through the
+ *         tree edge above v = sum of b over the subtree of v);
+ *   down: root to leaves: x[v] = x[parent v] + f[v] / pw[v]. */
+void orc_tree_solve(int64_t n, const int64_t *parent, const double *pw, const int64_t *order, int k,
+                    const double *b, double *x) {
+    double *f = (double *)malloc((size_t)n * (size_t)k * sizeof(double));
+    memcpy(f, b, (size_t)n * (size_t)k * sizeof(double));
+    for (int64_t i = n - 1; i >= 1; i--) {
+        int64_t v = order[i], p = parent[v];
+        for (int j = 0; j < k; j++) f[(size_t)p * k + j] += f[(size_t)v * k + j];
+    }
+    int64_t root = order[0];
+    for (int j = 0; j < k; j++) x[(size_t)root * k + j] = 0.0;
+    for (int64_t i = 1; i < n; i++) {
+        int64_t v = order[i], p = parent[v];
+        for (int j = 0; j < k; j++) x[(size_t)v * k + j] = x[(size_t)p * k + j] + f[(size_t)v * k + j] / pw[v];
+    }
+    free(f);
+}
+
+/* ============================================ subgraph solve (Sec. IV-C.1, IV-D) */
+
+/* Solve the grounded system L_P x = b (root row and column removed, x[root] = 0)
+ * by preconditioned conjugate gradients, one column at a time, with the grounded
+ * tree solve as the preconditioner (the paper solves L_P with AMG; the north-star
+ * design uses PCG with the tree). x0 = 0; stop when ||r||_2 <= rtol ||b||_2 over
+ * the non-root rows. Returns the largest iteration count over the columns and
+ * writes the largest final relative residual to *resid. */
+int orc_pcg(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w, const uint8_t *inP,
+            const int64_t *parent, const double *pw, const int64_t *order, int k, const double *b, double *x,
+            double rtol, int maxit, double *resid) {
+    int64_t root = order[0];
+    double *r = (double *)malloc((size_t)n * sizeof(double));
+    double *z = (double *)malloc((size_t)n * sizeof(double));
+    double *p = (double *)malloc((size_t)n * sizeof(double));
+    double *q = (double *)malloc((size_t)n * sizeof(double));
+    double *xc = (double *)malloc((size_t)n * sizeof(double));
+    int worst = 0;
+    double worst_res = 0.0;
+    for (int j = 0; j < k; j++) {
+        for (int64_t v = 0; v < n; v++) {
+            r[v] = b[(size_t)v * k + j];
+            xc[v] = 0.0;
+        }
+        r[root] = 0.0;
+        double bnorm = 0.0;
+        for (int64_t v = 0; v < n; v++) bnorm += r[v] * r[v];
+        bnorm = sqrt(bnorm);
+        int it = 0;
+        double rn = bnorm;
+        if (bnorm > 0.0) {
+            orc_tree_solve(n, parent, pw, order, 1, r, z);
+            memcpy(p, z, (size_t)n * sizeof(double));
+            double rz = 0.0;
+            for (int64_t v = 0; v < n; v++) rz += r[v] * z[v];
+            while (it < maxit) {
+                it++;
+                orc_laplacian_apply(n, m, src, dst, w, inP, 1, p, q);
+                q[root] = 0.0;
+                double pq = 0.0;
+                for (int64_t v = 0; v < n; v++) pq += p[v] * q[v];
+                double alpha = rz / pq;
+                for (int64_t v = 0; v < n; v++) {
+                    xc[v] += alpha * p[v];
+                    r[v] -= alpha * q[v];
+                }
+                rn = 0.0;
+                for (int64_t v = 0; v < n; v++) rn += r[v] * r[v];
+                rn = sqrt(rn);
+                if (rn <= rtol * bnorm) break;
+                orc_tree_solve(n, parent, pw, order, 1, r, z);
+                double rz_new = 0.0;
+                for (int64_t v = 0; v < n; v++) rz_new += r[v] * z[v];
+                double beta = rz_new / rz;
+                rz = rz_new;
+                for (int64_t v = 0; v < n; v++) p[v] = z[v] + beta * p[v];
+            }
+        }
+        for (int64_t v = 0; v < n; v++) x[(size_t)v * k + j] = xc[v];
+        if (it > worst) worst = it;
+        double rel = bnorm > 0.0 ? rn / bnorm : 0.0;
+        if (rel > worst_res) worst_res = rel;
+    }
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(xc);
+    if (resid) *resid = worst_res;
+    return worst;
+}
+
+/* ======================================================= random vectors (eq. 28) */
+
+/* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11): ten rounds of the 4x64 S-P network with multipliers
+ * 0xD2E7470EE14C6C93, 0xCA5A826395121157 and key increments (Weyl constants)
+ * 0x9E3779B97F4A7C15, 0xBB67AE8584CAA73B. Pure bijection of the counter. */
+void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]) {
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; r++) {
+        __uint128_t p0 = (__uint128_t)0xD2E7470EE14C6C93ull * c0;
+        __uint128_t p1 = (__uint128_t)0xCA5A826395121157ull * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+/* Start vectors h_0 of eq. (28): for node v and vector j of densification pass
+ * `pass`, counter (v, j, pass, 0) and key (seed, 0) give words x0, x1; with
+ * u_a = ((x0 >> 11) + 1/2) 2^-53 and u_b = ((x1 >> 11) + 1/2) 2^-53 the Box-Muller
+ * normal is sqrt(-2 ln u_a) cos(2 pi u_b). Each vector then has its mean
+ * removed so that 1'h_0 = 0. h0 is n x k row-major. */
+void orc_gauss_vectors(int64_t n, int k, uint64_t seed, int64_t pass, double *h0) {
+    const double two_pi = 6.283185307179586476925286766559;
+    uint64_t key[2] = {seed, 0};
+    for (int64_t v = 0; v < n; v++)
+        for (int j = 0; j < k; j++) {
+            uint64_t ctr[4] = {(uint64_t)v, (uint64_t)j, (uint64_t)pass, 0}, o[4];
+            orc_philox4x64_10(ctr, key, o);
+            double ua = ((double)(o[0] >> 11) + 0.5) * 0x1.0p-53;
+            double ub = ((double)(o[1] >> 11) + 0.5) * 0x1.0p-53;
+            h0[(size_t)v * k + j] = sqrt(-2.0 * log(ua)) * cos(two_pi * ub);
+        }
+    for (int j = 0; j < k; j++) {
+        double s = 0.0;
+        for (int64_t v = 0; v < n; v++) s += h0[(size_t)v * k + j];
+        double mean = s / (double)n;
+        for (int64_t v = 0; v < n; v++) h0[(size_t)v * k + j] -= mean;
+    }
+}
+
+/* =================================== embedding + scoring of one pass (Sec. III-F) */
+
+/* One pass of spectral off-tree edge embedding for the subgraph P = {e : inP[e]}
+ * whose spanning tree is {e : inP[e] == 1}:
+ *   h_0 from eq. (28); then t times h <- L_P^+ (L_G h)            (eq. 29);
+ *   heat[e] = w_e sum_j (h_j[p] - h_j[q])^2 for every edge (eqs. 31, 35, 55);
+ *   num_j = sum over E, den_j = sum over P of w_e (h_j[p] - h_j[q])^2, so that
+ *   num_j / den_j is the Rayleigh quotient h'L_G h / h'L_P h (eqs. 2, 4);
+ *   lambda_max = max_j num_j / den_j (Sec. IV-C.1), continuing the same vectors
+ *   to lambda_steps >= t steps when asked;
+ *   lambda_min = min_v L_G(v,v) / L_P(v,v)                           (eq. 61);
+ *   heat_max = max heat over the edges not in P (eq. 58).
+ * Returns 0, or -1 when the tree edges do not span G. */
+int orc_embed(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w, const uint8_t *inP,
+              int k, int t, int lambda_steps, uint64_t seed, int64_t pass, double pcg_rtol, int pcg_maxit,
+              double *heat, orc_pass_stats *st) {
+    int64_t *parent = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    double *pw = (double *)malloc((size_t)n * sizeof(double));
+    uint8_t *tree = (uint8_t *)malloc((size_t)m);
+    int64_t added = 0;
+    for (int64_t e = 0; e < m; e++) {
+        tree[e] = inP[e] == 1;
+        added += inP[e] == 2;
+    }
+    if (orc_root_tree(n, m, src, dst, w, tree, 0, parent, pw, order) != 0) {
+        free(parent); free(order); free(pw); free(tree);
+        return -1;
+    }
+    size_t nk = (size_t)n * (size_t)k;
+    double *h = (double *)malloc(nk * sizeof(double));
+    double *y = (double *)malloc(nk * sizeof(double));
+    orc_gauss_vectors(n, k, seed, pass, h);
+    int pcg_total = 0;
+    double pcg_res = 0.0;
+    int steps = lambda_steps > t ? lambda_steps : t;
+    double *num = (double *)calloc((size_t)k, sizeof(double));
+    double *den = (double *)calloc((size_t)k, sizeof(double));
+    memset(st, 0, sizeof(*st));
+    for (int s = 1; s <= steps; s++) {
+        if (s > t) { /* continued power steps only feed the Rayleigh quotient, which is
+                        scale-invariant per vector: normalise each vector to avoid overflow */
+            for (int j = 0; j < k; j++) {
+                double mx = 0.0;
+                for (int64_t v = 0; v < n; v++) mx = fmax(mx, fabs(h[(size_t)v * k + j]));
+                if (mx > 0.0)
+                    for (int64_t v = 0; v < n; v++) h[(size_t)v * k + j] /= mx;
+            }
+        }
+        orc_laplacian_apply(n, m, src, dst, w, NULL, k, h, y);
+        if (added == 0) {
+            orc_tree_solve(n, parent, pw, order, k, y, h);
+        } else {
+            double res = 0.0;
+            pcg_total += orc_pcg(n, m, src, dst, w, inP, parent, pw, order, k, y, h, pcg_rtol, pcg_maxit, &res);
+            if (res > pcg_res) pcg_res = res;
+        }
+        if (s == t) {
+            double hmax = 0.0;
+            for (int j = 0; j < k; j++) num[j] = den[j] = 0.0;
+            for (int64_t e = 0; e < m; e++) {
+                const double *hp = h + (size_t)src[e] * k, *hq = h + (size_t)dst[e] * k;
+                double acc = 0.0;
+                for (int j = 0; j < k; j++) {
+                    double d = hp[j] - hq[j];
+                    double c = w[e] * d * d;
+                    acc += d * d;
+                    num[j] += c;
+                    if (inP[e]) den[j] += c;
+                }
+                heat[e] = w[e] * acc;
+                if (!inP[e] && heat[e] > hmax) hmax = heat[e];
+            }
+            st->heat_max = hmax;
+        }
+    }
+    if (steps > t) { /* Rayleigh quotient of the vectors continued to lambda_steps */
+        for (int j = 0; j < k; j++) num[j] = den[j] = 0.0;
+        for (int64_t e = 0; e < m; e++) {
+            const double *hp = h + (size_t)src[e] * k, *hq = h + (size_t)dst[e] * k;
+            for (int j = 0; j < k; j++) {
+                double d = hp[j] - hq[j];
+                double c = w[e] * d * d;
+                num[j] += c;
+                if (inP[e]) den[j] += c;
+            }
+        }
+    }
+    double lmax = 0.0;
+    for (int j = 0; j < k; j++) {
+        double r = num[j] / den[j];
+        if (j == 0 || r > lmax) lmax = r;
+    }
+    double *dG = (double *)malloc((size_t)n * sizeof(double));
+    double *dP = (double *)malloc((size_t)n * sizeof(double));
+    orc_weighted_degree(n, m, src, dst, w, NULL, dG);
+    orc_weighted_degree(n, m, src, dst, w, inP, dP);
+    double lmin = 0.0;
+    for (int64_t v = 0; v < n; v++) {
+        double r = dG[v] / dP[v];
+        if (v == 0 || r < lmin) lmin = r;
+    }
+    int64_t moff = 0;
+    for (int64_t e = 0; e < m; e++) moff += inP[e] == 0;
+    st->lambda_max = lmax;
+    st->lambda_min = lmin;
+    st->kappa = lmax / lmin;
+    st->m_off = moff;
+    st->added_total = added;
+    st->pcg_iters = pcg_total;
+    st->pcg_resid = pcg_res;
+    free(dG); free(dP); free(num); free(den);
+    free(h); free(y);
+    free(parent); free(order); free(pw); free(tree);
+    return 0;
+}
+
+/* ============================================ filtering + similarity (Sec. IV-B, IV-D) */
+
+/* theta_sigma = (sigma2 lambda_min / lambda_max)^(2t+1) of eq. (58), the power
+ * taken by 2t repeated multiplications so that any caller reproduces it bit for
+ * bit from the same three FP64 inputs. */
+double orc_theta(double sigma2, double lambda_min, double lambda_max, int t) {
+    double base = sigma2 * lambda_min / lambda_max;
+    double r = base;
+    for (int i = 0; i < 2 * t; i++) r *= base;
+    return r;
+}
+
+static const double *g_sort_h;
+static int cmp_desc_h_asc_id(const void *a, const void *b) {
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    double hx = g_sort_h[x], hy = g_sort_h[y];
+    if (hx > hy) return -1;
+    if (hx < hy) return 1;
+    return (x > y) - (x < y);
+}
+
+/* Filter and add (eq. (58), Sec. IV-D steps 5 and 6):
+ *   candidates C = {e not in P : heat_e >= theta * heat_max}, the comparison made
+ *   in FP64, ranked by heat descending then id ascending (Sec. III-I step 4);
+ *   walk C in rank order; an edge whose two endpoints are both already marked is
+ *   "similar" to an edge taken in this pass and is skipped; an accepted edge marks
+ *   its endpoints (sim_hops >= 0) and their neighbours in G (sim_hops >= 1);
+ *   sim_hops < 0 disables the check; stop after `budget` acceptances (budget <= 0:
+ *   no limit). Accepted edges get inP[e] = 2. Returns the number accepted and the
+ *   candidate count in *ncand. */
+int64_t orc_filter_select(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *heat,
+                          uint8_t *inP, double theta, double heat_max, int sim_hops, int64_t budget,
+                          int64_t *ncand) {
+    double thr = theta * heat_max;
+    int64_t c = 0;
+    int64_t *cand = (int64_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int64_t));
+    for (int64_t e = 0; e < m; e++)
+        if (!inP[e] && heat[e] >= thr) cand[c++] = e;
+    g_sort_h = heat;
+    qsort(cand, (size_t)c, sizeof(int64_t), cmp_desc_h_asc_id);
+    if (ncand) *ncand = c;
+    /* G adjacency for the one-hop marks */
+    int64_t *rp = NULL, *adj = NULL;
+    if (sim_hops >= 1) {
+        rp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+        for (int64_t e = 0; e < m; e++) {
+            rp[src[e] + 1]++;
+            rp[dst[e] + 1]++;
+        }
+        for (int64_t v = 0; v < n; v++) rp[v + 1] += rp[v];
+        adj = (int64_t *)malloc((size_t)(2 * m) * sizeof(int64_t));
+        int64_t *fill = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+        for (int64_t v = 0; v < n; v++) fill[v] = rp[v];
+        for (int64_t e = 0; e < m; e++) {
+            adj[fill[src[e]]++] = dst[e];
+            adj[fill[dst[e]]++] = src[e];
+        }
+        free(fill);
+    }
+    uint8_t *mark = (uint8_t *)calloc((size_t)n, 1);
+    int64_t acc = 0;
+    for (int64_t i = 0; i < c; i++) {
+        if (budget > 0 && acc >= budget) break;
+        int64_t e = cand[i];
+        int64_t p = src[e], q = dst[e];
+        if (sim_hops >= 0 && mark[p] && mark[q]) continue;
+        inP[e] = 2;
+        acc++;
+        if (sim_hops >= 0) {
+            mark[p] = mark[q] = 1;
+            if (sim_hops >= 1) {
+                for (int64_t a = rp[p]; a < rp[p + 1]; a++) mark[adj[a]] = 1;
+                for (int64_t a = rp[q]; a < rp[q + 1]; a++) mark[adj[a]] = 1;
+            }
+        }
+    }
+    free(mark);
+    free(rp);
+    free(adj);
+    free(cand);
+    return acc;
+}
+
+/* ================================================ densification loop (Sec. IV-D) */
+
+/* Iterative densification. P starts as the maximum-weight spanning tree (or the
+ * caller's init_mask: 1 = tree edge, 2 = added edge). Each pass embeds and scores
+ * (orc_embed), estimates lambda_max, lambda_min and kappa = lambda_max / lambda_min
+ * (eq. 3), and stops when kappa <= sigma2, when no off-P edge is left, or when the
+ * pass index reaches max_iters; otherwise it filters and adds edges
+ * (orc_filter_select) and starts the next pass with fresh vectors. mask gets
+ * 1 / 2 / 0 (tree / added / not in P); scores get heat / heat_max of the last
+ * pass that filtered (of the final pass when none did), 0 for edges already in P
+ * at that pass. trace (optional, trace_cap entries) gets one record per pass.
+ * Returns ORC_OK, ORC_NOT_CONVERGED (kappa > sigma2 at the end) or an error. */
+int orc_sparsify(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                 const orc_opts *o, const uint8_t *init_mask, uint8_t *mask, double *scores, orc_summary *sum,
+                 orc_pass_stats *trace, int trace_cap) {
+    int rc = orc_validate(n, m, src, dst, w);
+    if (rc != ORC_OK) return rc;
+    if (o->k < 1 || o->t < 1 || !(o->sigma2 >= 1.0)) return ORC_ERR_INVALID;
+    if (init_mask) {
+        memcpy(mask, init_mask, (size_t)m);
+    } else {
+        orc_max_spanning_tree(n, m, src, dst, w, mask);
+    }
+    int64_t tree_edges = 0;
+    for (int64_t e = 0; e < m; e++) tree_edges += mask[e] == 1;
+    double *heat = (double *)malloc((size_t)m * sizeof(double));
+    int64_t budget = 0;
+    if (o->budget_frac > 0.0) {
+        budget = (int64_t)floor(o->budget_frac * (double)n);
+        if (budget < 1) budget = 1;
+    }
+    memset(scores, 0, (size_t)m * sizeof(double));
+    int filtered = 0;
+    orc_pass_stats st;
+    int64_t pass = 0;
+    int64_t scored = 0;
+    for (;;) {
+        if (orc_embed(n, m, src, dst, w, mask, o->k, o->t, o->lambda_steps, o->seed, pass, o->pcg_rtol,
+                      o->pcg_max_iters, heat, &st) != 0) {
+            free(heat);
+            return ORC_ERR_INVALID;
+        }
+        st.pass = pass;
+        scored += st.m_off;
+        int stop = st.kappa <= o->sigma2 || st.m_off == 0 || pass >= o->max_iters;
+        if (!stop) {
+            st.theta = orc_theta(o->sigma2, st.lambda_min, st.lambda_max, o->t);
+            for (int64_t e = 0; e < m; e++) scores[e] = mask[e] ? 0.0 : heat[e] / st.heat_max;
+            filtered = 1;
+            st.accepted = orc_filter_select(n, m, src, dst, heat, mask, st.theta, st.heat_max, o->sim_hops, budget,
+                                            &st.candidates);
+        } else if (!filtered) {
+            for (int64_t e = 0; e < m; e++)
+                scores[e] = (mask[e] || st.heat_max <= 0.0) ? 0.0 : heat[e] / st.heat_max;
+        }
+        if (trace && pass < trace_cap) trace[pass] = st;
+        if (stop) break;
+        pass++;
+    }
+    int64_t added = 0;
+    for (int64_t e = 0; e < m; e++) added += mask[e] == 2;
+    sum->lambda_max = st.lambda_max;
+    sum->lambda_min = st.lambda_min;
+    sum->kappa = st.kappa;
+    sum->heat_max = st.heat_max;
+    sum->pcg_resid = st.pcg_resid;
+    sum->passes = (int32_t)(pass + 1);
+    sum->tree_edges = tree_edges;
+    sum->added_edges = added;
+    sum->scored_edges = scored;
+    free(heat);
+    return (st.kappa <= o->sigma2) ? ORC_OK : ORC_NOT_CONVERGED;
+}
+
+/* ===================================================== test utilities (eqs. 6-8) */
+
+/* Stretch of every edge with respect to the tree {e : tree[e] == 1} (eq. 7):
+ * st(p,q) = w_pq * sum over the tree path from p to q of 1 / w_f. Tree edges get
+ * stretch 1. Returns the total stretch of eq. (6). Quadratic-time path walk. */
+double orc_tree_stretch(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                        const uint8_t *tree, double *stretch) {
+    int64_t *parent = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *order = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    double *pw = (double *)malloc((size_t)n * sizeof(double));
+    int64_t *depth = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    double total = -1.0;
+    if (orc_root_tree(n, m, src, dst, w, tree, 0, parent, pw, order) == 0) {
+        depth[order[0]] = 0;
+        for (int64_t i = 1; i < n; i++) depth[order[i]] = depth[parent[order[i]]] + 1;
+        total = 0.0;
+        for (int64_t e = 0; e < m; e++) {
+            int64_t a = src[e], b = dst[e];
+            double r = 0.0;
+            while (a != b) {
+                if (depth[a] >= depth[b]) {
+                    r += 1.0 / pw[a];
+                    a = parent[a];
+                } else {
+                    r += 1.0 / pw[b];
+                    b = parent[b];
+                }
+            }
+            stretch[e] = w[e] * r;
+            total += stretch[e];
+        }
+    }
+    free(parent); free(order); free(pw); free(depth);
+    return total;
+}
