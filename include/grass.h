@@ -1,0 +1,170 @@
+/*
+ * grass.h -- C ABI of the MI355X (gfx950) GRASS spectral sparsification library.
+ *
+ * What it computes (Feng, "GRASS: Graph Spectral Sparsification Leveraging
+ * Scalable Spectral Perturbation Analysis", arXiv:1911.04382):
+ *   - a spanning-tree backbone P of a weighted undirected graph G (Sec. III-I
+ *     step 1; here the maximum-weight tree, ties broken by the smaller edge id);
+ *   - t-step generalized power iterations h_t = (L_P^+ L_G)^t h_0 on k random
+ *     vectors orthogonal to the all-ones vector (eqs. 28, 29);
+ *   - the Joule heat w_pq sum_j (h_j(p) - h_j(q))^2 of every off-subgraph edge
+ *     (eqs. 31, 35, 55);
+ *   - lambda_max by a Rayleigh quotient of the iterated vectors (Sec. IV-C.1),
+ *     lambda_min by the degree ratio of eq. (61), kappa = lambda_max/lambda_min
+ *     (eq. 3);
+ *   - the normalized-heat threshold theta = (sigma2 lambda_min/lambda_max)^(2t+1)
+ *     of eq. (58), a similarity check and a per-pass budget (Sec. IV-D steps 5, 6),
+ *     repeated as iterative densification until kappa <= sigma2 (Sec. IV-D).
+ *
+ * Conventions shared by every call:
+ *   - A graph is a canonical edge list: src[e] < dst[e], edges sorted by
+ *     (src, dst), no duplicates, 0 <= ids < n, weights finite and > 0; the edge
+ *     id is the position e. Arrays are DEVICE pointers owned by the caller.
+ *   - Every output is indexed by edge id (or node id), whatever node order the
+ *     kernels use internally.
+ *   - All work is enqueued on the caller's stream. Calls that must decide on
+ *     device results (densification passes, PCG convergence) synchronize that
+ *     stream; the outputs are complete when the call returns.
+ *   - Device memory comes from the caller's workspace (`workspace`, `ws_bytes`,
+ *     at least grass_workspace_bytes()). Passing workspace == NULL makes the
+ *     context allocate and keep its own (grown on demand, freed by
+ *     grass_destroy).
+ *   - Negative status = failure: outputs are undefined and grass_last_error()
+ *     holds a message. No exception crosses the ABI. A context is not
+ *     thread-safe; use one per host thread.
+ *   - Results are deterministic: the same inputs give the same output bits
+ *     (no floating-point atomics; every reduction has a fixed order).
+ */
+#ifndef GRASS_H
+#define GRASS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GRASS_OK = 0,
+    GRASS_NOT_CONVERGED = 1,    /* warning: outputs valid, kappa > sigma2 after max_iters passes */
+    GRASS_ERR_INVALID = -1,     /* bad arguments or non-canonical graph */
+    GRASS_ERR_DISCONNECTED = -2,/* G is not connected (Sec. II-A assumes it is) */
+    GRASS_ERR_OOM = -3,         /* workspace too small / allocation failed */
+    GRASS_ERR_DEVICE = -4,      /* HIP runtime error or a device-side guard tripped */
+    GRASS_ERR_UNIMPLEMENTED = -5,
+    GRASS_ERR_CANCELLED = -6
+} grass_status;
+
+typedef struct grass_ctx grass_ctx;
+
+/* Create a context on HIP device `device`. */
+grass_status grass_create(int device, grass_ctx **out);
+/* Destroy a context (frees only memory the context allocated itself). */
+void grass_destroy(grass_ctx *ctx);
+/* Text of the last failure on this context ("" if none). Valid until the next call. */
+const char *grass_last_error(const grass_ctx *ctx);
+
+/* Graph of the conventions above. src, dst: int32 [m]; w: float64 [m]; device. */
+typedef struct {
+    int64_t n, m;
+    const int32_t *src;
+    const int32_t *dst;
+    const double *w;
+} grass_graph;
+
+/* Options (grass_opts_default() gives the defaults in brackets). */
+typedef struct {
+    double sigma2;          /* target relative condition number, eq. (5) [100] */
+    int32_t k;              /* random vectors, 1..64 [16] */
+    int32_t t;              /* power steps per pass, eq. (29) [2] */
+    uint64_t seed;          /* Philox key of the start vectors [0] */
+    int32_t max_iters;      /* densification passes; 0 = estimate only [50] */
+    double budget_frac;     /* per-pass budget floor(budget_frac n) (>= 1); 0 = unlimited [0.01] */
+    int32_t sim_hops;       /* similarity marks: -1 off, 0 endpoints, 1 endpoints + neighbours [1] */
+    int32_t lambda_steps;   /* power steps for lambda_max (>= t continues the vectors) [0 = t] */
+    double pcg_rtol;        /* relative residual target of every L_P solve, checked in FP64 [1e-6] */
+    int32_t pcg_max_iters;  /* inner PCG iterations per refinement step [2000] */
+    double pcg_inner_rtol;  /* inner FP32 PCG reduction per refinement step [1e-3] */
+    int32_t pcg_max_outer;  /* FP64 refinement steps per solve [6] */
+    int32_t precision;      /* 32: FP32 vectors (FP64 sums); 64: FP64 throughout [32] */
+    const uint8_t *init_mask; /* optional device [m]: 1 = edge of a caller-given spanning tree,
+                                 2 = already-added edge, 0 = off; NULL = compute the tree */
+} grass_opts;
+
+grass_opts grass_opts_default(void);
+
+/* Per-pass record. */
+typedef struct {
+    int32_t pass;
+    double lambda_max, lambda_min, kappa, theta, heat_max;
+    int64_t m_off;          /* off-subgraph edges scored in this pass */
+    int64_t candidates;     /* edges passing eq. (58) */
+    int64_t accepted;       /* edges added after the similarity check and budget */
+    int64_t pcg_iters;      /* inner PCG iterations summed over the pass's solves (max over vectors) */
+    double pcg_resid64;     /* largest FP64 relative residual of the pass's L_P solves */
+    double ms;              /* wall time of the pass */
+} grass_pass_stats;
+
+typedef struct {
+    double lambda_max, lambda_min, kappa; /* estimates on the final subgraph */
+    double pcg_resid64;     /* FP64 relative residual of the last L_P solve (0 if only tree solves) */
+    double heat_max;
+    int32_t passes;
+    int64_t tree_edges, added_edges;
+    int64_t scored_edges;   /* sum over passes of m_off */
+    int64_t pcg_iters;
+} grass_summary;
+
+/* Outputs of grass_sparsify. edge_mask, scores: device [m]; summary, trace: host. */
+typedef struct {
+    uint8_t *edge_mask;     /* 1 tree, 2 added, 0 not in the sparsifier */
+    void *scores;           /* float32 (precision 32) or float64 (precision 64): heat/heat_max of the
+                               last pass that filtered (the final pass if none did); 0 for edges in P */
+    grass_summary *summary; /* may be NULL */
+    grass_pass_stats *trace;/* may be NULL */
+    int32_t trace_cap;
+} grass_result;
+
+/* Workspace bytes that grass_sparsify / grass_embed / grass_spanning_tree need for
+ * a graph of n nodes and m edges under opts (the admission footprint). */
+size_t grass_workspace_bytes(int64_t n, int64_t m, const grass_opts *opts);
+
+/* The whole method: tree, passes of embedding + scoring + estimates, filtering
+ * and densification until kappa <= sigma2 (Sec. IV-D). Returns GRASS_OK,
+ * GRASS_NOT_CONVERGED or an error. */
+grass_status grass_sparsify(grass_ctx *ctx, const grass_graph *g, const grass_opts *opts, void *workspace,
+                            size_t ws_bytes, grass_result *res, void *stream);
+
+/* Maximum-weight spanning tree (Boruvka; ties by smaller edge id): tree_mask[e] = 1
+ * for the n-1 tree edges, else 0. tree_mask: device uint8 [m]. */
+grass_status grass_spanning_tree(grass_ctx *ctx, const grass_graph *g, uint8_t *tree_mask, void *workspace,
+                                 size_t ws_bytes, void *stream);
+
+/* One pass of embedding and scoring for a given subgraph P (Sec. III-F, eqs. 28-35,
+ * 55, 61): p_mask device uint8 [m] (1 = spanning-tree edge, 2 = added edge, 0 = off;
+ * the 1-edges must span G); pass = the Philox counter word of the start vectors.
+ * heat: device [m], float32 or float64 per opts->precision, the unnormalized heat of
+ * every edge (scaled by a power of two common to all edges: only ratios are
+ * meaningful); stats: host, filled except candidates/accepted/theta. */
+grass_status grass_embed(grass_ctx *ctx, const grass_graph *g, const uint8_t *p_mask, const grass_opts *opts,
+                         int32_t pass, void *heat, grass_pass_stats *stats, void *workspace, size_t ws_bytes,
+                         void *stream);
+
+/* Filtering and similarity check of one pass (eq. 58, Sec. IV-D steps 5-6): given
+ * the heat of grass_embed and the pass's lambda estimates, add the accepted edges to
+ * p_mask (value 2, in place) and write stats->theta/candidates/accepted.
+ * scores (optional device [m], same type as heat): heat/heat_max off P, 0 in P. */
+grass_status grass_select(grass_ctx *ctx, const grass_graph *g, uint8_t *p_mask, const grass_opts *opts,
+                          const void *heat, double lambda_max, double lambda_min, grass_pass_stats *stats,
+                          void *scores, void *workspace, size_t ws_bytes, void *stream);
+
+/* Start vectors h_0 of eq. (28): n x k row-major, float32 or float64 per precision,
+ * Philox4x64-10 Gaussians with each vector's mean removed. out: device. */
+grass_status grass_start_vectors(grass_ctx *ctx, int64_t n, int32_t k, uint64_t seed, int32_t pass,
+                                 int32_t precision, void *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRASS_H */

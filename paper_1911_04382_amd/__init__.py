@@ -1,0 +1,291 @@
+"""Python binding of libgrass.so, the gfx950 GRASS spectral sparsification
+library (C ABI in include/grass.h).
+
+The binding only marshals arguments: every step of the computation runs in the
+library's HIP kernels. Tensors are torch tensors on a ROCm device; PyTorch is used
+for device memory and streams only. There is no CPU fallback: if the library is
+missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrass.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "grass.h")
+
+OK, NOT_CONVERGED = 0, 1
+ERR_INVALID, ERR_DISCONNECTED, ERR_OOM, ERR_DEVICE, ERR_UNIMPLEMENTED, ERR_CANCELLED = -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_DISCONNECTED", -3: "ERR_OOM",
+                -4: "ERR_DEVICE", -5: "ERR_UNIMPLEMENTED", -6: "ERR_CANCELLED"}
+
+
+class GrassError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class grass_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("w", ctypes.c_void_p)]
+
+
+class grass_opts(ctypes.Structure):
+    _fields_ = [
+        ("sigma2", ctypes.c_double), ("k", ctypes.c_int32), ("t", ctypes.c_int32), ("seed", ctypes.c_uint64),
+        ("max_iters", ctypes.c_int32), ("budget_frac", ctypes.c_double), ("sim_hops", ctypes.c_int32),
+        ("lambda_steps", ctypes.c_int32), ("pcg_rtol", ctypes.c_double), ("pcg_max_iters", ctypes.c_int32),
+        ("pcg_inner_rtol", ctypes.c_double), ("pcg_max_outer", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("init_mask", ctypes.c_void_p),
+    ]
+
+
+class grass_pass_stats(ctypes.Structure):
+    _fields_ = [
+        ("pass_", ctypes.c_int32), ("lambda_max", ctypes.c_double), ("lambda_min", ctypes.c_double),
+        ("kappa", ctypes.c_double), ("theta", ctypes.c_double), ("heat_max", ctypes.c_double),
+        ("m_off", ctypes.c_int64), ("candidates", ctypes.c_int64), ("accepted", ctypes.c_int64),
+        ("pcg_iters", ctypes.c_int64), ("pcg_resid64", ctypes.c_double), ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f[0].rstrip("_"): getattr(self, f[0]) for f in self._fields_}
+
+
+class grass_summary(ctypes.Structure):
+    _fields_ = [
+        ("lambda_max", ctypes.c_double), ("lambda_min", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("pcg_resid64", ctypes.c_double), ("heat_max", ctypes.c_double), ("passes", ctypes.c_int32),
+        ("tree_edges", ctypes.c_int64), ("added_edges", ctypes.c_int64), ("scored_edges", ctypes.c_int64),
+        ("pcg_iters", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+class grass_result(ctypes.Structure):
+    _fields_ = [("edge_mask", ctypes.c_void_p), ("scores", ctypes.c_void_p),
+                ("summary", ctypes.POINTER(grass_summary)), ("trace", ctypes.POINTER(grass_pass_stats)),
+                ("trace_cap", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgrass.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1911_04382_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    st = ctypes.c_int
+    L.grass_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp)]
+    L.grass_create.restype = st
+    L.grass_destroy.argtypes = [vp]
+    L.grass_destroy.restype = None
+    L.grass_last_error.argtypes = [vp]
+    L.grass_last_error.restype = ctypes.c_char_p
+    L.grass_opts_default.argtypes = []
+    L.grass_opts_default.restype = grass_opts
+    L.grass_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(grass_opts)]
+    L.grass_workspace_bytes.restype = ctypes.c_size_t
+    L.grass_sparsify.argtypes = [vp, ctypes.POINTER(grass_graph), ctypes.POINTER(grass_opts), vp, ctypes.c_size_t,
+                                 ctypes.POINTER(grass_result), vp]
+    L.grass_sparsify.restype = st
+    L.grass_spanning_tree.argtypes = [vp, ctypes.POINTER(grass_graph), vp, vp, ctypes.c_size_t, vp]
+    L.grass_spanning_tree.restype = st
+    L.grass_embed.argtypes = [vp, ctypes.POINTER(grass_graph), vp, ctypes.POINTER(grass_opts), i32, vp,
+                              ctypes.POINTER(grass_pass_stats), vp, ctypes.c_size_t, vp]
+    L.grass_embed.restype = st
+    L.grass_select.argtypes = [vp, ctypes.POINTER(grass_graph), vp, ctypes.POINTER(grass_opts), vp, dbl, dbl,
+                               ctypes.POINTER(grass_pass_stats), vp, vp, ctypes.c_size_t, vp]
+    L.grass_select.restype = st
+    L.grass_start_vectors.argtypes = [vp, i64, i32, u64, i32, i32, vp, vp]
+    L.grass_start_vectors.restype = st
+    _lib = L
+    return L
+
+
+def exported_symbols_declared_in_header(header: str = HEADER):
+    """Names of the functions include/grass.h declares."""
+    import re
+
+    text = open(header).read()
+    return sorted(set(re.findall(r"\b(grass_[a-z_]+)\s*\(", text)))
+
+
+# ------------------------------------------------------------------ context
+class Context:
+    """One library context on one HIP device (grass_create / grass_destroy)."""
+
+    def __init__(self, device: int = 0):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        rc = self.lib.grass_create(device, ctypes.byref(h))
+        if rc != OK:
+            raise GrassError(rc, f"grass_create({device}) failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.grass_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return self.lib.grass_last_error(self.h).decode()
+
+    def check(self, rc):
+        if rc < 0:
+            raise GrassError(rc, self.last_error())
+        return rc
+
+
+# ----------------------------------------------------------------- helpers
+def _torch():
+    import torch
+
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class DeviceGraph:
+    """A canonical graph held on the device (int32 src/dst, float64 w)."""
+
+    n: int
+    src: object
+    dst: object
+    w: object
+
+    @property
+    def m(self) -> int:
+        return int(self.src.shape[0])
+
+    def c(self) -> grass_graph:
+        return grass_graph(self.n, self.m, self.src.data_ptr(), self.dst.data_ptr(), self.w.data_ptr())
+
+
+def to_device(g, device="cuda:0") -> DeviceGraph:
+    """Copy a host graph (numpy arrays n, src, dst, w) to the device."""
+    torch = _torch()
+    return DeviceGraph(int(g.n), torch.as_tensor(g.src, dtype=torch.int32).to(device),
+                       torch.as_tensor(g.dst, dtype=torch.int32).to(device),
+                       torch.as_tensor(g.w, dtype=torch.float64).to(device))
+
+
+def make_opts(**kw) -> grass_opts:
+    o = load_library().grass_opts_default()
+    for k, v in kw.items():
+        if k == "init_mask":
+            o.init_mask = None if v is None else v.data_ptr()
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def workspace(g: DeviceGraph, opts: grass_opts, device="cuda:0"):
+    """A uint8 device tensor of grass_workspace_bytes()."""
+    torch = _torch()
+    nbytes = load_library().grass_workspace_bytes(g.n, g.m, ctypes.byref(opts))
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def _ws_args(ws):
+    if ws is None:
+        return None, 0
+    return ctypes.c_void_p(ws.data_ptr()), int(ws.numel())
+
+
+# ------------------------------------------------------- the C-ABI calls
+@dataclass
+class SparsifyResult:
+    status: int
+    mask: object
+    scores: object
+    summary: dict
+    trace: list = field(default_factory=list)
+
+
+def grass_sparsify(ctx: Context, g: DeviceGraph, opts: grass_opts, ws=None, stream=None, trace_cap=256):
+    torch = _torch()
+    dev = g.src.device
+    mask = torch.empty(g.m, dtype=torch.uint8, device=dev)
+    scores = torch.empty(g.m, dtype=torch.float64 if opts.precision == 64 else torch.float32, device=dev)
+    summ = grass_summary()
+    tr = (grass_pass_stats * trace_cap)()
+    res = grass_result(mask.data_ptr(), scores.data_ptr(), ctypes.pointer(summ),
+                       ctypes.cast(tr, ctypes.POINTER(grass_pass_stats)), trace_cap)
+    gc = g.c()
+    wsp, wsb = _ws_args(ws)
+    rc = ctx.check(ctx.lib.grass_sparsify(ctx.h, ctypes.byref(gc), ctypes.byref(opts), wsp, wsb, ctypes.byref(res),
+                                          _stream_ptr(stream)))
+    trace = [tr[i].as_dict() for i in range(min(summ.passes, trace_cap))]
+    return SparsifyResult(rc, mask, scores, summ.as_dict(), trace)
+
+
+def grass_spanning_tree(ctx: Context, g: DeviceGraph, ws=None, stream=None):
+    torch = _torch()
+    mask = torch.empty(g.m, dtype=torch.uint8, device=g.src.device)
+    gc = g.c()
+    wsp, wsb = _ws_args(ws)
+    ctx.check(ctx.lib.grass_spanning_tree(ctx.h, ctypes.byref(gc), ctypes.c_void_p(mask.data_ptr()), wsp, wsb,
+                                          _stream_ptr(stream)))
+    return mask
+
+
+def grass_embed(ctx: Context, g: DeviceGraph, p_mask, opts: grass_opts, pass_=0, ws=None, stream=None):
+    torch = _torch()
+    heat = torch.empty(g.m, dtype=torch.float64 if opts.precision == 64 else torch.float32, device=g.src.device)
+    st = grass_pass_stats()
+    gc = g.c()
+    wsp, wsb = _ws_args(ws)
+    ctx.check(ctx.lib.grass_embed(ctx.h, ctypes.byref(gc), ctypes.c_void_p(p_mask.data_ptr()), ctypes.byref(opts),
+                                  pass_, ctypes.c_void_p(heat.data_ptr()), ctypes.byref(st), wsp, wsb,
+                                  _stream_ptr(stream)))
+    return heat, st.as_dict()
+
+
+def grass_select(ctx: Context, g: DeviceGraph, p_mask, opts: grass_opts, heat, lambda_max, lambda_min, ws=None,
+                 stream=None, want_scores=True):
+    """Filter + similarity check of one pass; p_mask is updated in place."""
+    torch = _torch()
+    scores = torch.empty_like(heat) if want_scores else None
+    st = grass_pass_stats()
+    gc = g.c()
+    wsp, wsb = _ws_args(ws)
+    ctx.check(ctx.lib.grass_select(ctx.h, ctypes.byref(gc), ctypes.c_void_p(p_mask.data_ptr()), ctypes.byref(opts),
+                                   ctypes.c_void_p(heat.data_ptr()), float(lambda_max), float(lambda_min),
+                                   ctypes.byref(st), None if scores is None else ctypes.c_void_p(scores.data_ptr()),
+                                   wsp, wsb, _stream_ptr(stream)))
+    return scores, st.as_dict()
+
+
+def grass_start_vectors(ctx: Context, n, k, seed, pass_=0, precision=32, device="cuda:0", stream=None):
+    torch = _torch()
+    out = torch.empty((n, k), dtype=torch.float64 if precision == 64 else torch.float32, device=device)
+    ctx.check(ctx.lib.grass_start_vectors(ctx.h, n, k, seed, pass_, precision, ctypes.c_void_p(out.data_ptr()),
+                                          _stream_ptr(stream)))
+    return out
+
+
+def grass_workspace_bytes(n, m, opts: grass_opts) -> int:
+    return int(load_library().grass_workspace_bytes(n, m, ctypes.byref(opts)))

@@ -1,0 +1,62 @@
+// Embedding kernels (embed.hip): start vectors, Laplacian products, the
+// level-scheduled tree solve, PCG on L_P with FP64 refinement, edge scoring.
+#pragma once
+#include "state.h"
+
+namespace grass {
+
+// reduction slots in Vecs::red (kMaxK doubles each)
+enum : int {
+    RED_NUM = 0, RED_DEN, RED_LMAX, RED_PQ, RED_RZ, RED_RZN, RED_RR, RED_RR0, RED_ALPHA, RED_BETA,
+    RED_BN, RED_RN, RED_MEAN, RED_SCRATCH, RED_SLOTS = 16
+};
+// u64 slots in Vecs::u64s
+enum : int { U_HMAX = 0, U_LMIN = 1, U_ABSMAX = 2, U_SLOTS = 8 };
+
+template <typename T>
+void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v);
+
+// h0 of eq. (28) into out (n x k, row stride k).
+template <typename T>
+void start_vectors(const Dims &d, uint64_t seed, int pass, T *out, Vecs<T> &v, hipStream_t s);
+
+// y = L x over a CSR (difference form), optional grounding of `root`, optional
+// scaling of y by the power of two that brings max|x| (u64 slot) to [1, 2), optional
+// per-block partials of x.y.
+template <typename T>
+void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const T *x, T *y, int root,
+               const unsigned long long *scale_from, double *dot_part, hipStream_t s);
+
+// Grounded tree solve x = L_T^+ y (x[root] = 0): up-sweep then down-sweep over the
+// heavy-light levels. x may alias y. Optional fused outputs of the down-sweep:
+// per-tile partials of rdot.x, max|x| (u64 slot bits of a double).
+template <typename T>
+void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
+                unsigned long long *absmax, hipStream_t s);
+
+// L_P solve by FP32 (or FP64) PCG with the tree preconditioner, refined in FP64
+// until ||b - L_P x||_2 <= rtol ||b||_2 per vector. Returns inner iterations
+// (max over vectors, summed over refinement steps) and the FP64 relative residual.
+struct SolveInfo {
+    long long iters = 0;
+    double resid64 = 0.0;
+    int outer = 0;
+};
+template <typename T>
+SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s);
+
+// Score every edge: heat (optional output), FP64 per-vector sums over E and over P,
+// max heat over the edges not in P. Then reduce to lambda_max (host reads).
+struct PassScalars {
+    double lambda_max = 0, lambda_min = 0, heat_max = 0;
+};
+template <typename T>
+void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStream_t s);
+template <typename T>
+PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s);
+
+// max|x| of an n x k block into the absmax slot
+template <typename T>
+void absmax_of(const Dims &d, const T *x, unsigned long long *slot, hipStream_t s);
+
+}  // namespace grass

@@ -1,0 +1,99 @@
+// Device-resident state of one graph: the CSR of L_G, the subgraph P, the rooted
+// spanning tree and its heavy-light solve layout, the vectors of the power
+// iterations and the PCG buffers. Every pointer lives in one Arena.
+#pragma once
+#include "common.h"
+
+namespace grass {
+
+constexpr int kMaxLevels = 64;   // light depth <= log2(n) < 32; margin
+constexpr int kSolveThreads = 256;
+constexpr int kSolveNPR = 8;     // nodes per run in the tree-solve scans
+constexpr int kMaxK = 64;
+
+enum : uint8_t { SEG_TOP = 1, SEG_BOT = 2 };
+
+// Sizes that fix the workspace plan.
+struct Dims {
+    long long n = 0, m = 0;
+    int k = 1, kp = 1, prec = 32;
+    int TN = 0;          // tree-solve tile, nodes
+    long long Npad = 0;  // padded layout length bound
+    long long ntiles = 0;
+};
+
+inline Dims make_dims(long long n, long long m, int k, int prec) {
+    Dims d;
+    d.n = n;
+    d.m = m;
+    d.k = k;
+    d.kp = kpad(k);
+    d.prec = prec;
+    d.TN = kSolveNPR * kSolveThreads / d.kp;
+    d.Npad = n + (long long)kMaxLevels * d.TN;
+    d.ntiles = (d.Npad + d.TN - 1) / d.TN;
+    return d;
+}
+
+// Graph topology (precision-independent part).
+struct Topo {
+    long long n = 0, m = 0;
+    const int *src = nullptr, *dst = nullptr;
+    const double *w = nullptr;
+    int *rowptr = nullptr, *col = nullptr, *ceid = nullptr;  // CSR of G, rows sorted by neighbour
+    double *degG = nullptr;
+    unsigned *devflags = nullptr;  // device error bits
+    int *scal_i = nullptr;         // small integer scratch (counters)
+    // subgraph
+    uint8_t *mask = nullptr;       // [m] 1 tree / 2 added / 0 off
+    int *prow = nullptr, *pcol = nullptr;  // CSR of L_P
+    double *pval64 = nullptr;      // FP64 weights of L_P (refinement residual)
+    double *degP = nullptr;
+    // rooted tree
+    int *parent = nullptr, *heavy = nullptr, *head = nullptr, *off = nullptr, *ld = nullptr, *lp = nullptr;
+    double *pw = nullptr;
+    // layout
+    long long N = 0;               // used layout length (tile aligned)
+    int nlev = 0;
+    std::vector<long long> lvl_start;  // host: [nlev+1] positions (tile aligned)
+    int *perm = nullptr;           // [Npad] node or -1
+    uint8_t *flags = nullptr;      // [Npad]
+    int *ptop = nullptr;           // [Npad]
+    int *lc_ptr = nullptr;         // [Npad+1]
+    int *lc_pos = nullptr;         // [n]
+    // tile scan state
+    unsigned *status = nullptr;    // [ntiles]
+    int *hs = nullptr;             // [ntiles]
+    int *tickets = nullptr;        // [2*kMaxLevels]
+    unsigned epoch = 0;
+    // scratch for setup and selection
+    ScanTmp scan;
+    SortTmp sort;
+    int *tmpA = nullptr, *tmpB = nullptr;  // [max(2m, n+1)] selection scratch
+    unsigned long long *keys = nullptr;  // [max(m, n)] sort keys of the selection
+    int *greedy_mark = nullptr, *greedy_owner = nullptr;  // [n]
+    uint8_t *cand_acc = nullptr;   // [m]
+};
+
+// Precision-dependent buffers.
+template <typename T>
+struct Vecs {
+    T *wT = nullptr;      // [m] edge weights
+    T *cval = nullptr;    // [2m] CSR(G) weights
+    T *pval = nullptr;    // [2m] CSR(P) weights
+    T *rpw = nullptr;     // [Npad] 1/parent weight in layout order
+    T *H = nullptr, *Y = nullptr;  // [n*kp]
+    T *F = nullptr;       // [Npad*kp] subtree currents (layout order)
+    T *agg = nullptr;     // [ntiles*kp]
+    T *heat = nullptr;    // [m] (internal heat when the caller gives none)
+    // PCG
+    T *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dx = nullptr;  // [n*kp]
+    double *x64 = nullptr, *r64 = nullptr;  // [n*kp]
+    // reductions
+    double *part = nullptr;   // [ntiles*kp*2] per-block partials
+    double *red = nullptr;    // [16*kMaxK] reduced vectors (num, den, rz, pq, rr, rr0, bnorm, ...)
+    int *active = nullptr;    // [kMaxK] PCG column flags + count at [kMaxK-1]
+    unsigned long long *u64s = nullptr;  // [8]: heat max bits, lambda_min bits, absmax bits
+};
+
+}  // namespace grass

@@ -1,0 +1,221 @@
+"""Parity of the gfx950 library (through the C ABI) with the FP64 oracle on the
+same seeded inputs.
+
+Bars (see the readings list): integer work (tree, edge ids, selection given the
+same scores) bit-exact; FP64 runs within 1e-10; FP32 normalized scores within
+1e-4 of the oracle's and within 1e-4 relative for edges above the cutoff band;
+lambda estimates within 1e-4 relative (lambda_min, an exact ratio of FP64
+degrees, within 1e-12)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1911_04382_amd import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a ROCm GPU", allow_module_level=True)
+
+import paper_1911_04382_amd as grass  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = grass.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def tree_graphs():
+    return [
+        G.config_c1(),
+        G.grid2d(37, 29, seed=5),
+        G.mesh3d(13, 11, 9, weights=(G.W_LOGUNIFORM10, -3, 3), seed=2),
+        G.random_connected(3000, 6000, weights=(G.W_UNIFORM, 1.0, 4.0), seed=3),
+        G.Graph(*(lambda g: (g.n, g.src, g.dst, np.floor(g.w)))(G.random_connected(2000, 5000, seed=4))),  # ties
+        G.cycle(257),  # all weights equal
+        G.rgg(3000, seed=1),
+        G.ba(4000, seed=2),
+        G.grid2d_longrange(60, seed=3),
+    ]
+
+
+@pytest.mark.parametrize("idx", range(9))
+def test_spanning_tree_bit_exact(ctx, idx):
+    g = tree_graphs()[idx]
+    say("tree parity:", g.name, g.n, g.m)
+    dg = grass.to_device(g, DEV)
+    mask = grass.grass_spanning_tree(ctx, dg).cpu().numpy()
+    ref = O.max_spanning_tree(g)
+    assert np.array_equal(mask, ref)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_start_vectors(ctx, precision):
+    n, k = 5003, 8
+    say("start vectors", precision)
+    h = grass.grass_start_vectors(ctx, n, k, 1234, 3, precision).cpu().numpy().astype(np.float64)
+    ref = O.gauss_vectors(n, k, 1234, 3)
+    tol = 1e-13 if precision == 64 else 2e-7
+    np.testing.assert_allclose(h, ref, rtol=tol, atol=tol * np.abs(ref).max())
+
+
+def _norm_err(heat, ref, off):
+    s = heat / heat[off].max()
+    r = ref / ref[off].max()
+    return np.abs(s - r)[off].max(), s, r
+
+
+EMBED_CASES = [
+    ("c1_fp64", lambda: G.config_c1(), 8, 2, 64),
+    ("c1_fp32", lambda: G.config_c1(), 8, 2, 32),
+    ("mesh_k32", lambda: G.mesh3d(14, 13, 12, weights=(G.W_LOGUNIFORM10, -3, 3), seed=1), 32, 2, 32),
+    ("powergrid_t3", lambda: G.grid2d_longrange(70, seed=2), 16, 3, 32),
+    ("ba_k16", lambda: G.ba(3000, seed=5), 16, 2, 32),
+    ("rgg_k5", lambda: G.rgg(2500, seed=7), 5, 2, 32),
+]
+
+
+@pytest.mark.parametrize("case", EMBED_CASES, ids=[c[0] for c in EMBED_CASES])
+def test_embed_tree_pass(ctx, case):
+    name, mk, k, t, prec = case
+    g = mk()
+    say("embed tree pass:", name, g.n, g.m, k, t, prec)
+    tmask = O.max_spanning_tree(g)
+    dg = grass.to_device(g, DEV)
+    pm = torch.as_tensor(tmask).to(DEV)
+    opts = grass.make_opts(k=k, t=t, precision=prec, seed=11)
+    heat, st = grass.grass_embed(ctx, dg, pm, opts, pass_=2)
+    heat = heat.cpu().numpy().astype(np.float64)
+    ref = O.embed(g, tmask, k=k, t=t, seed=11, pass_=2)
+    off = tmask == 0
+    err, s, r = _norm_err(heat, ref.heat, off)
+    tol = 1e-10 if prec == 64 else 1e-4
+    say(f"  max normalized score error {err:.3e}; lambda_max {st['lambda_max']:.6g} vs {ref.stats['lambda_max']:.6g}")
+    assert err <= tol
+    assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-10 if prec == 64 else 1e-4)
+    assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
+    assert st["m_off"] == off.sum()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_embed_with_added_edges_pcg(ctx, prec):
+    g = G.grid2d(40, 40, seed=3) if prec == 64 else G.mesh3d(16, 15, 14, weights=(G.W_LOGUNIFORM10, -3, 3), seed=4)
+    k = 8 if prec == 64 else 16
+    say("embed PCG pass:", g.name, prec)
+    tmask = O.max_spanning_tree(g)
+    r0 = O.embed(g, tmask, k=k, t=2, seed=0)
+    th = O.theta(100.0, r0.stats["lambda_min"], r0.stats["lambda_max"], 2)
+    P, acc, _ = O.filter_select(g, r0.heat, tmask, th, r0.stats["heat_max"], sim_hops=1, budget=max(1, g.n // 100))
+    assert acc > 0
+    dg = grass.to_device(g, DEV)
+    pm = torch.as_tensor(P).to(DEV)
+    # FP64 runs solve L_P to the oracle's own tolerance; FP32 runs use the default 1e-6
+    opts = grass.make_opts(k=k, t=2, precision=prec, seed=0, pcg_rtol=1e-12 if prec == 64 else 1e-6)
+    heat, st = grass.grass_embed(ctx, dg, pm, opts, pass_=1)
+    heat = heat.cpu().numpy().astype(np.float64)
+    ref = O.embed(g, P, k=k, t=2, seed=0, pass_=1)
+    off = P == 0
+    err, s, r = _norm_err(heat, ref.heat, off)
+    say(f"  pcg iters {st['pcg_iters']}, resid64 {st['pcg_resid64']:.2e}, max score err {err:.3e}")
+    assert st["pcg_resid64"] <= opts.pcg_rtol
+    assert err <= (1e-10 if prec == 64 else 1e-4)
+    assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
+    assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
+
+
+@pytest.mark.parametrize("hops", [1, 0, -1])
+def test_select_bit_exact_given_scores(ctx, hops):
+    g = G.grid2d(48, 40, seed=9)
+    say("select parity, hops", hops)
+    tmask = O.max_spanning_tree(g)
+    dg = grass.to_device(g, DEV)
+    opts = grass.make_opts(k=8, t=2, precision=32, seed=1, sim_hops=hops, budget_frac=0.01 if hops >= 0 else 0.004)
+    pm = torch.as_tensor(tmask).to(DEV)
+    heat, st = grass.grass_embed(ctx, dg, pm, opts, pass_=0)
+    scores, sel = grass.grass_select(ctx, dg, pm, opts, heat, st["lambda_max"], st["lambda_min"])
+    gpu_mask = pm.cpu().numpy()
+    h64 = heat.cpu().numpy().astype(np.float64)  # the GPU's FP32 scores, exactly
+    th = O.theta(100.0, st["lambda_min"], st["lambda_max"], 2)
+    assert sel["theta"] == th
+    hmax = h64[tmask == 0].max()
+    budget = max(1, int(np.floor(opts.budget_frac * g.n)))
+    P, acc, nc = O.filter_select(g, h64, tmask, th, hmax, sim_hops=hops, budget=budget)
+    say(f"  candidates {nc} accepted {acc}")
+    assert sel["candidates"] == nc and sel["accepted"] == acc
+    assert np.array_equal(gpu_mask, P)
+    s = scores.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(s[tmask == 0], h64[tmask == 0] / hmax, rtol=1e-6)
+
+
+def test_sparsify_c1_fp64_one_pass(ctx):
+    g = G.config_c1()
+    say("sparsify C1 FP64 one pass")
+    dg = grass.to_device(g, DEV)
+    opts = grass.make_opts(k=8, t=2, precision=64, seed=0, max_iters=1, sigma2=100.0)
+    res = grass.grass_sparsify(ctx, dg, opts)
+    ref = O.sparsify(g, sigma2=100.0, k=8, t=2, seed=0, max_iters=1)
+    mask = res.mask.cpu().numpy()
+    assert np.array_equal(mask, ref.mask)
+    np.testing.assert_allclose(res.scores.cpu().numpy(), ref.scores, atol=1e-10)
+    assert res.summary["lambda_max"] == pytest.approx(ref.summary["lambda_max"], rel=1e-8)
+    assert res.summary["passes"] == ref.summary["passes"] == 2
+    assert res.status == ref.status
+
+
+@pytest.mark.parametrize("case", ["grid", "mesh"])
+def test_sparsify_iterative_fp32(ctx, case):
+    if case == "grid":
+        g, k = G.grid2d(32, 32, seed=2), 8
+    else:
+        g, k = G.mesh3d(12, 12, 12, weights=(G.W_LOGUNIFORM10, -3, 3), seed=0), 16
+    say("sparsify iterative FP32:", g.name)
+    dg = grass.to_device(g, DEV)
+    opts = grass.make_opts(k=k, t=2, precision=32, seed=0, sigma2=20.0 if case == "grid" else 100.0)
+    res = grass.grass_sparsify(ctx, dg, opts)
+    ref = O.sparsify(g, sigma2=opts.sigma2, k=k, t=2, seed=0)
+    mask = res.mask.cpu().numpy()
+    say("  gpu", res.summary, "\n  ora", ref.summary)
+    assert np.array_equal(mask == 1, ref.mask == 1)  # identical trees
+    diff = np.flatnonzero(mask != ref.mask)
+    assert len(diff) <= max(2, int(0.05 * (ref.mask == 2).sum())), diff
+    assert res.summary["passes"] == ref.summary["passes"]
+    # determinism: same inputs, same bits
+    res2 = grass.grass_sparsify(ctx, dg, opts)
+    assert torch.equal(res.mask, res2.mask) and torch.equal(res.scores, res2.scores)
+
+
+def test_error_paths(ctx):
+    g = G.grid2d(8, 8)
+    keep = (g.src != 0) & (g.dst != 0)
+    disc = G.Graph(g.n, g.src[keep], g.dst[keep], g.w[keep])
+    opts = grass.make_opts(k=4)
+    with pytest.raises(grass.GrassError) as e:
+        grass.grass_sparsify(ctx, grass.to_device(disc, DEV), opts)
+    assert e.value.status == grass.ERR_DISCONNECTED
+    uns = G.Graph(g.n, g.src[::-1].copy(), g.dst[::-1].copy(), g.w.copy())
+    with pytest.raises(grass.GrassError) as e:
+        grass.grass_sparsify(ctx, grass.to_device(uns, DEV), opts)
+    assert e.value.status == grass.ERR_INVALID
+    bad = G.Graph(g.n, g.src.copy(), g.dst.copy(), g.w.copy())
+    bad.w[5] = -1.0
+    with pytest.raises(grass.GrassError) as e:
+        grass.grass_sparsify(ctx, grass.to_device(bad, DEV), opts)
+    assert e.value.status == grass.ERR_INVALID
+    dg = grass.to_device(g, DEV)
+    tiny = torch.empty(1024, dtype=torch.uint8, device=DEV)
+    with pytest.raises(grass.GrassError) as e:
+        grass.grass_sparsify(ctx, dg, opts, ws=tiny)
+    assert e.value.status == grass.ERR_OOM
+    # a caller-provided workspace of the advertised size works
+    ws = grass.workspace(dg, opts, DEV)
+    res = grass.grass_sparsify(ctx, dg, opts, ws=ws)
+    assert res.status in (grass.OK, grass.NOT_CONVERGED)
