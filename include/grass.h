@@ -164,6 +164,27 @@ grass_status grass_select(grass_ctx *ctx, const grass_graph *g, uint8_t *p_mask,
 grass_status grass_start_vectors(grass_ctx *ctx, int64_t n, int32_t k, uint64_t seed, int32_t pass,
                                  int32_t precision, void *out, void *stream);
 
+/* Diagnostics: out = A'B (k x k, FP64, row-major, device) for device n x k row-major
+ * blocks A, B (float32 or float64 per precision), computed by the same Gram kernel
+ * (MFMA for FP32 with k in 9..32) that the block PCG of the L_P solves uses. */
+grass_status grass_gram(grass_ctx *ctx, int64_t n, int32_t k, int32_t precision, const void *a, const void *b,
+                        double *out, void *stream);
+
+/* Diagnostics: per-kernel-family timing with HIP events recorded on the call's
+ * stream (adds a few microseconds per timed launch). grass_profile_enable resets
+ * the counters; grass_profile_read copies up to cap records (name, launches,
+ * summed milliseconds, summed algorithmic bytes: the bytes the operation must
+ * move, each vector row read once) and returns the number written (the number
+ * available when out is NULL). */
+typedef struct {
+    const char *name;
+    int64_t launches;
+    double total_ms;
+    double alg_bytes;
+} grass_kernel_stats;
+grass_status grass_profile_enable(grass_ctx *ctx, int32_t enable);
+int32_t grass_profile_read(const grass_ctx *ctx, grass_kernel_stats *out, int32_t cap);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,11 @@ class grass_summary(ctypes.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
+class grass_kernel_stats(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double)]
+
+
 class grass_result(ctypes.Structure):
     _fields_ = [("edge_mask", ctypes.c_void_p), ("scores", ctypes.c_void_p),
                 ("summary", ctypes.POINTER(grass_summary)), ("trace", ctypes.POINTER(grass_pass_stats)),
@@ -109,6 +114,12 @@ def load_library(path: str = LIB_PATH):
     L.grass_select.restype = st
     L.grass_start_vectors.argtypes = [vp, i64, i32, u64, i32, i32, vp, vp]
     L.grass_start_vectors.restype = st
+    L.grass_gram.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp]
+    L.grass_gram.restype = st
+    L.grass_profile_enable.argtypes = [vp, i32]
+    L.grass_profile_enable.restype = st
+    L.grass_profile_read.argtypes = [vp, ctypes.POINTER(grass_kernel_stats), i32]
+    L.grass_profile_read.restype = i32
     _lib = L
     return L
 
@@ -147,6 +158,17 @@ class Context:
 
     def last_error(self) -> str:
         return self.lib.grass_last_error(self.h).decode()
+
+    def profile(self, enable: bool = True):
+        """Enable (and reset) per-kernel-family event timing (grass_profile_enable)."""
+        self.check(self.lib.grass_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        n = self.lib.grass_profile_read(self.h, None, 0)
+        arr = (grass_kernel_stats * n)()
+        got = self.lib.grass_profile_read(self.h, arr, n)
+        return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].total_ms,
+                                       "alg_bytes": arr[i].alg_bytes} for i in range(got)}
 
     def check(self, rc):
         if rc < 0:
@@ -284,6 +306,17 @@ def grass_start_vectors(ctx: Context, n, k, seed, pass_=0, precision=32, device=
     out = torch.empty((n, k), dtype=torch.float64 if precision == 64 else torch.float32, device=device)
     ctx.check(ctx.lib.grass_start_vectors(ctx.h, n, k, seed, pass_, precision, ctypes.c_void_p(out.data_ptr()),
                                           _stream_ptr(stream)))
+    return out
+
+
+def grass_gram(ctx: Context, a, b, stream=None):
+    """A'B (float64, k x k) of two device n x k tensors (float32 or float64)."""
+    torch = _torch()
+    n, k = a.shape
+    out = torch.empty((k, k), dtype=torch.float64, device=a.device)
+    prec = 64 if a.dtype == torch.float64 else 32
+    ctx.check(ctx.lib.grass_gram(ctx.h, n, k, prec, ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)))
     return out
 
 

@@ -7,6 +7,8 @@
 
 #include "embed.h"
 #include "graph.h"
+#include "kern.h"
+#include "profiler.h"
 #include "select.h"
 
 struct grass_ctx {
@@ -14,9 +16,11 @@ struct grass_ctx {
     std::string last_error;
     void *own_ws = nullptr;
     size_t own_bytes = 0;
+    grass::Profiler prof;
 };
 
 namespace grass {
+thread_local Profiler *g_prof = nullptr;
 namespace {
 
 // Everything one call needs, planned over one arena.
@@ -105,6 +109,7 @@ void setup(Session<T> &S, const grass_graph &g, const uint8_t *p_mask, bool need
     if (need_tree) {
         build_tree<T>(t, S.v, S.d, S.st, s);
         build_pcsr<T>(t, S.v, s);
+        S.d.p_nnz = read_i32(t.prow + t.n, s);
     }
     init_greedy_state(t, s);
     fill_u32(t.devflags, 4, 0u, s);
@@ -203,12 +208,17 @@ grass_status sparsify_impl(grass_ctx *ctx, const grass_graph &g, const grass_opt
         ps.pcg_resid64 = pr.resid64;
         if (!stop) {
             ps.theta = theta_of(o.sigma2, pr.sc.lambda_min, pr.sc.lambda_max, o.t);
-            SelectOut so = select_edges<T>(t, S.d, S.v.heat, ps.theta, pr.sc.heat_max, o.sim_hops, budget, scores, s);
+            SelectOut so;
+            {
+                ProfScope sc(PK_SELECT, 0.0, s);
+                so = select_edges<T>(t, S.d, S.v.heat, ps.theta, pr.sc.heat_max, o.sim_hops, budget, scores, s);
+            }
             ps.candidates = so.candidates;
             ps.accepted = so.accepted;
             filtered = true;
             added += so.accepted;
             build_pcsr<T>(t, S.v, s);
+            S.d.p_nnz = read_i32(t.prow + t.n, s);
         } else if (!filtered && scores) {
             normalized_scores<T>(t, S.v.heat, pr.sc.heat_max, scores, s);
         }
@@ -296,8 +306,16 @@ grass_status select_impl(grass_ctx *ctx, const grass_graph &g, uint8_t *p_mask, 
 template <typename F>
 grass_status guarded(grass_ctx *ctx, F f) {
     if (!ctx) return GRASS_ERR_INVALID;
+    struct Bind {
+        Bind(Profiler *p) { g_prof = p; }
+        ~Bind() {
+            if (g_prof) g_prof->resolve();
+            g_prof = nullptr;
+        }
+    };
     try {
         GR_HIP(hipSetDevice(ctx->device));
+        Bind bind(&ctx->prof);
         grass_status st = f();
         ctx->last_error.clear();
         return st;
@@ -461,6 +479,49 @@ grass_status grass_start_vectors(grass_ctx *ctx, int64_t n, int32_t k, uint64_t 
         GR_HIP(hipStreamSynchronize(s));
         return GRASS_OK;
     });
+}
+
+grass_status grass_gram(grass_ctx *ctx, int64_t n, int32_t k, int32_t precision, const void *a, const void *b,
+                        double *out, void *stream) {
+    return guarded(ctx, [&]() -> grass_status {
+        require(n >= 1 && k >= 1 && k <= kMaxK && a && b && out, GRASS_ERR_INVALID, "bad Gram arguments");
+        require(precision == 32 || precision == 64, GRASS_ERR_INVALID, "precision must be 32 or 64");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        Dims d = make_dims(n, 1, k, precision);
+        size_t need = ((size_t)gram_blocks(d.kp) * d.kp * d.kp + (size_t)d.kp * d.kp + 64) * sizeof(double) + 1024;
+        Arena ar = bind_arena(ctx, nullptr, 0, need);
+        double *gpart = ar.take<double>((size_t)gram_blocks(d.kp) * d.kp * d.kp);
+        double *red = ar.take<double>((size_t)d.kp * d.kp);
+        if (precision == 64)
+            block_gram<double>(d, static_cast<const double *>(a), static_cast<const double *>(b), gpart, red, out, s);
+        else
+            block_gram<float>(d, static_cast<const float *>(a), static_cast<const float *>(b), gpart, red, out, s);
+        GR_HIP(hipStreamSynchronize(s));
+        return GRASS_OK;
+    });
+}
+
+grass_status grass_profile_enable(grass_ctx *ctx, int32_t enable) {
+    if (!ctx) return GRASS_ERR_INVALID;
+    ctx->prof.on = enable != 0;
+    ctx->prof.reset();
+    return GRASS_OK;
+}
+
+int32_t grass_profile_read(const grass_ctx *ctx, grass_kernel_stats *out, int32_t cap) {
+    static const char *names[PK_COUNT] = {"spmm_LG", "spmm_LP", "tree_solve", "score",
+                                          "pcg_vec", "resid64", "start_vectors", "select"};
+    if (!ctx) return 0;
+    int32_t n = 0;
+    for (int i = 0; i < PK_COUNT && n < cap; i++) {
+        if (!out) break;
+        out[n].name = names[i];
+        out[n].launches = ctx->prof.launches[i];
+        out[n].total_ms = ctx->prof.ms[i];
+        out[n].alg_bytes = ctx->prof.bytes[i];
+        n++;
+    }
+    return out ? n : PK_COUNT;
 }
 
 }  // extern "C"

@@ -55,6 +55,23 @@ void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStr
 template <typename T>
 PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s);
 
+// fixed-order column sums of per-block partials part[b * stride + offset + j]
+template <typename T>
+void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride, int offset, double *out,
+             hipStream_t s);
+
+// Inner block PCG (block size k, tree preconditioner): on entry r holds the
+// right-hand side (grounded row zeroed) and red[RED_RN] its squared column norms;
+// on exit dx approximates L_P^+ r to a relative residual itol per vector, r holds
+// the residual. Returns the iteration count.
+template <typename T>
+long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it, hipStream_t s);
+
+// Diagnostics: C = A'B (k x k, FP64, row-major) with the block-PCG Gram kernel;
+// gpart needs kPersist * kp * kp doubles, red kp * kp.
+template <typename T>
+void block_gram(const Dims &d, const T *A, const T *B, double *gpart, double *red, double *out, hipStream_t s);
+
 // max|x| of an n x k block into the absmax slot
 template <typename T>
 void absmax_of(const Dims &d, const T *x, unsigned long long *slot, hipStream_t s);

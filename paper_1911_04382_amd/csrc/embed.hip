@@ -6,35 +6,15 @@
 // HBM traffic (or latency), so the design work is coalescing, fusion and the
 // block -> XCD mapping, not MFMA.
 #include "embed.h"
+#include "kern.h"
+#include "profiler.h"
 
 namespace grass {
 
-#define KP_DISPATCH(kp, ...)                                                                    \
-    switch (kp) {                                                                               \
-    case 1: { constexpr int KP = 1; __VA_ARGS__; } break;                                       \
-    case 2: { constexpr int KP = 2; __VA_ARGS__; } break;                                       \
-    case 4: { constexpr int KP = 4; __VA_ARGS__; } break;                                       \
-    case 8: { constexpr int KP = 8; __VA_ARGS__; } break;                                       \
-    case 16: { constexpr int KP = 16; __VA_ARGS__; } break;                                     \
-    case 32: { constexpr int KP = 32; __VA_ARGS__; } break;                                     \
-    case 64: { constexpr int KP = 64; __VA_ARGS__; } break;                                     \
-    default: throw Error(GRASS_ERR_INVALID, "k must be in 1..64");                              \
-    }
-
 namespace {
 
-constexpr int kThreads = 256;
 constexpr int kGaussBlocksMax = 2048;
-constexpr int kRowsPerGroup = 16;   // Laplacian rows per lane group
 constexpr int kEdgesPerGroup = 16;  // scored edges per lane group
-
-// 8 XCDs: consecutive workgroup ids land on different XCDs; remap them so that each
-// XCD works on one contiguous range of rows (its L2 then holds the neighbourhood).
-__device__ __forceinline__ int xcd_block(int bid, int grid) {
-    int per = grid >> 3;
-    return (bid & 7) * per + (bid >> 3);
-}
-inline int xcd_grid(int nb) { return (nb + 7) / 8 * 8; }
 
 // ------------------------------------------------------------ start vectors
 // Philox4x64-10 of Salmon et al. (SC'11); counter (v, j, pass, 0), key (seed, 0).
@@ -77,21 +57,34 @@ __global__ __launch_bounds__(kThreads) void k_gauss_sum(long long n, int k, unsi
     }
 }
 
+// Column sums of per-block partials (part[b * stride + offset + j]) in a fixed
+// order: 1024 threads, thread (g, j) adds blocks g, g + G, ... with four
+// interleaved accumulators, then the groups are combined in order.
 template <int KP>
-__global__ void k_col_sum(const double *__restrict__ part, int nblk, int stride, int offset, double scale,
-                          double *__restrict__ out) {
-    constexpr int G = kThreads / KP;
+__global__ __launch_bounds__(kColThreads) void k_col_sum(const double *__restrict__ part, int nblk, int stride,
+                                                         int offset, double scale, double *__restrict__ out) {
+    // block c reduces partial blocks [c * chunk, (c + 1) * chunk) into out[c * KP + j]
+    constexpr int G = kColThreads / KP;
     __shared__ double sh[G][KP];
+    int chunk = (nblk + gridDim.x - 1) / gridDim.x;
+    int lo = blockIdx.x * chunk, hi = min(nblk, lo + chunk);
     int g = threadIdx.x / KP, j = threadIdx.x % KP;
-    double s = 0.0;
-    for (int b = g; b < nblk; b += G) s += part[(long long)b * stride + offset + j];
-    sh[g][j] = s;
-    __syncthreads();
-    if (g == 0) {
-        double t = 0.0;
-        for (int q = 0; q < G; q++) t += sh[q][j];
-        out[j] = t * scale;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = lo + g;
+    for (; b + 3 * G < hi; b += 4 * G) {
+        a0 += part[(long long)b * stride + offset + j];
+        a1 += part[(long long)(b + G) * stride + offset + j];
+        a2 += part[(long long)(b + 2 * G) * stride + offset + j];
+        a3 += part[(long long)(b + 3 * G) * stride + offset + j];
     }
+    for (; b < hi; b += G) a0 += part[(long long)b * stride + offset + j];
+    sh[g][j] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    for (int w = G / 2; w > 0; w >>= 1) {
+        if (g < w) sh[g][j] += sh[g + w][j];
+        __syncthreads();
+    }
+    if (g == 0) out[(long long)blockIdx.x * KP + j] = sh[0][j] * scale;
 }
 
 template <typename T, int KP>
@@ -113,30 +106,65 @@ __device__ __forceinline__ double pow2_scale(const unsigned long long *slot) {
     return ldexp(1.0, -ilogb(mx));
 }
 
+// y = L x for the rows of one block: the block's CSR slice (row pointers,
+// neighbour ids, weights) is staged in LDS with coalesced loads, so every row then
+// costs only the gathers of its neighbours' vector rows (k contiguous values).
+// Difference form: y_v = sum_u w_vu (x_v - x_u) keeps FP32 accurate for smooth x.
+template <int KP>
+struct LapShape {
+    static constexpr int G = kThreads / KP;            // lane groups per block
+    static constexpr int RPB = G * 4;                  // rows per block
+    static constexpr int CAP = RPB * 12 < 3072 ? RPB * 12 : 3072;  // staged nonzeros (fast path)
+};
+
 template <typename T, int KP>
 __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int *__restrict__ rowptr,
                                                   const int *__restrict__ col, const T *__restrict__ val,
                                                   const T *__restrict__ x, T *__restrict__ y, int root,
                                                   const unsigned long long *__restrict__ scale_from,
                                                   double *__restrict__ dot_part, int nblk) {
-    constexpr int G = kThreads / KP;
-    constexpr int RPB = G * kRowsPerGroup;
+    constexpr int G = LapShape<KP>::G;
+    constexpr int RPB = LapShape<KP>::RPB;
+    constexpr int CAP = LapShape<KP>::CAP;
+    __shared__ int s_ptr[RPB + 1];
+    __shared__ int s_col[CAP];
+    __shared__ T s_val[CAP];
     int b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= nblk) return;
-    int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    const int tid = threadIdx.x;
+    const int g = tid / KP, j = tid % KP;
+    const long long r0 = (long long)b * RPB;
+    const int nrows = (int)min((long long)RPB, n - r0);
+    for (int i = tid; i <= nrows; i += kThreads) s_ptr[i] = rowptr[r0 + i];
+    __syncthreads();
+    const int base = s_ptr[0], nnz = s_ptr[nrows] - base;
+    const bool staged = nnz <= CAP;
+    if (staged)
+        for (int i = tid; i < nnz; i += kThreads) {
+            s_col[i] = col[base + i];
+            s_val[i] = val[base + i];
+        }
+    __syncthreads();
     const T sc = (T)pow2_scale(scale_from);
     double dacc = 0.0;
-    long long r0 = (long long)b * RPB;
     if (j < k) {
-        for (int i = g; i < RPB; i += G) {
+        for (int i = g; i < nrows; i += G) {
             long long v = r0 + i;
-            if (v >= n) break;
             T xv = x[v * k + j];
             T acc = 0;
-            int pe = rowptr[v + 1];
-            for (int p = rowptr[v]; p < pe; p++) {
-                int u = col[p];
-                acc += val[p] * (xv - x[(long long)u * k + j]);
+            int p = s_ptr[i] - base, pe = s_ptr[i + 1] - base;
+            if (staged) {
+                for (; p + 3 < pe; p += 4) {
+                    T x0 = x[(long long)s_col[p] * k + j], x1 = x[(long long)s_col[p + 1] * k + j];
+                    T x2 = x[(long long)s_col[p + 2] * k + j], x3 = x[(long long)s_col[p + 3] * k + j];
+                    acc += s_val[p] * (xv - x0);
+                    acc += s_val[p + 1] * (xv - x1);
+                    acc += s_val[p + 2] * (xv - x2);
+                    acc += s_val[p + 3] * (xv - x3);
+                }
+                for (; p < pe; p++) acc += s_val[p] * (xv - x[(long long)s_col[p] * k + j]);
+            } else {
+                for (; p < pe; p++) acc += val[base + p] * (xv - x[(long long)col[base + p] * k + j]);
             }
             acc *= sc;
             if (v == root) acc = 0;
@@ -157,29 +185,34 @@ __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int 
 }
 
 // ------------------------------------------------------------ tree solve
-// One heavy-light level of a sweep, as a segmented scan over the level's layout
-// positions (paths are contiguous segments, top to bottom).
+// One sweep of the grounded tree solve over the heavy-light layout, all levels in
+// one launch. Paths are contiguous segments of the layout (top to bottom):
 //   UP   (reverse scan, segments start at path bottoms):
 //        f[i] = y[perm i] + sum_{light children c} f[c] + f[i+1]   (subtree currents)
 //   DOWN (forward scan, segments start at path tops):
 //        x[perm i] = x[parent of top] + sum_{top..i} f / pw        (potentials)
-// A tile publishes its aggregate before looking back; its carry-in is the sum of
-// the predecessors' aggregates back to the nearest tile holding a segment start,
-// added in a fixed order, so results never depend on timing. Tiles take their
-// index from an atomic ticket, so every awaited tile is already running; every
-// wait is bounded.
+// Tiles take an atomic ticket in processing order (UP: deepest level first,
+// tiles in reverse; DOWN: root level first). A tile first waits for the tiles
+// it depends on in other levels (precomputed lists: the tiles of its light
+// children, or of its paths' parents), then scans, publishes its aggregate,
+// looks back within its level to the nearest tile holding a segment start (adding
+// aggregates in a fixed order, so results never depend on timing), writes its
+// outputs and stamps itself done. Every awaited tile holds a smaller ticket, so
+// it is already running; every wait is bounded. Data another tile reads inside
+// the same launch moves through agent-scope (XCD-coherent) loads and stores.
 template <typename T, int KP, bool UP>
 __global__ __launch_bounds__(kThreads) void k_sweep(
-    long long level_pos, int ntiles, long long tile_base, int k, const int *__restrict__ perm,
-    const uint8_t *__restrict__ flags, const int *__restrict__ ptop, const int *__restrict__ lc_ptr,
-    const int *__restrict__ lc_pos, const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F,
-    T *__restrict__ xout, T *__restrict__ agg, int *__restrict__ hs, unsigned *__restrict__ status, unsigned epoch,
-    int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot, double *__restrict__ dot_part,
-    unsigned long long *__restrict__ absmax) {
+    int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm, const uint8_t *__restrict__ flags,
+    const int *__restrict__ ptop, const int *__restrict__ lc_ptr, const int *__restrict__ lc_pos,
+    const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F, T *__restrict__ xout,
+    T *__restrict__ agg, int *__restrict__ hs, unsigned *__restrict__ status, unsigned *__restrict__ done,
+    const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
+    int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
+    double *__restrict__ dot_part, unsigned long long *__restrict__ absmax) {
     constexpr int RUNS = kThreads / KP;
     constexpr int NPR = kSolveNPR;
     constexpr int TN = RUNS * NPR;
-    __shared__ int s_tile;
+    __shared__ int s_info[3];  // level's first tile, level's tile count, logical tile
     __shared__ T s_agg[RUNS][KP];
     __shared__ int s_hs[RUNS];
     __shared__ T s_excl[RUNS][KP];
@@ -187,43 +220,111 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
     __shared__ T s_carry[KP];
     __shared__ double s_red[RUNS][KP];
     __shared__ double s_max[kThreads / 64];
+    __shared__ int s_bad;
 
     const int tid = threadIdx.x;
     const int j = tid % KP, r = tid / KP;
-    if (tid == 0) s_tile = atomicAdd(ticket, 1);
+    const unsigned epoch = epoch_ptr[0] + (UP ? 0u : 1u);
+    if (tid == 0) {
+        int tk = atomicAdd(ticket, 1);
+        int acc = 0;
+        s_info[0] = 0;
+        s_info[1] = 1;
+        s_info[2] = 0;
+        for (int q = 0; q < nlev; q++) {
+            int l = UP ? (nlev - 1 - q) : q;
+            int f0 = lvl_tile[l], nt = lvl_tile[l + 1] - f0;
+            if (tk < acc + nt) {
+                int i = tk - acc;
+                s_info[0] = f0;
+                s_info[1] = nt;
+                s_info[2] = UP ? (nt - 1 - i) : i;
+                break;
+            }
+            acc += nt;
+        }
+        s_bad = 0;
+    }
     __syncthreads();
-    const int tk = s_tile;
-    const int lt = UP ? (ntiles - 1 - tk) : tk;  // logical tile within the level
-    const long long p0 = level_pos + (long long)lt * TN;
-    const long long gt = tile_base + lt;
+    const int lvl_first = s_info[0], ntiles = s_info[1], lt = s_info[2];
+    const long long gt = (long long)lvl_first + lt;
+    const long long p0 = gt * TN;
     const bool act = j < k;
 
-    // load + run-local inclusive segmented scan (scan order index s -> position)
+    // Everything that does not depend on other tiles is loaded first, so that the
+    // critical path through the levels keeps a single memory hop per tile.
     T vals[NPR];
-    bool pre[NPR];
-    bool seen = false;
-    T acc = 0;
+    int link[NPR];     // UP: first light child's position; DOWN: parent of the path top
+    int link2[NPR];    // UP: second light child's position (or -1)
+    int lcr[NPR];      // UP: index of the third light child (rare) in lc_pos, or -1
+    int lce[NPR];
+    int vid[NPR];      // node id of the position (-1: padding)
+    uint8_t fls[NPR];
 #pragma unroll
     for (int q = 0; q < NPR; q++) {
         int sidx = r * NPR + q;
         long long pos = p0 + (UP ? (TN - 1 - sidx) : sidx);
         uint8_t fl = flags[pos];
-        bool start = UP ? (fl & SEG_BOT) : (fl & SEG_TOP);
+        fls[q] = fl;
         T val = 0;
-        if (act) {
-            if (UP) {
-                int v = perm[pos];
-                if (v >= 0) val = yin[(long long)v * k + j];
-                int c1 = lc_ptr[pos + 1];
-                for (int c = lc_ptr[pos]; c < c1; c++) val += F[(long long)lc_pos[c] * k + j];
-            } else {
-                val = F[pos * k + j] * rpw[pos];
-                if (fl & SEG_TOP) {
-                    int pt = ptop[pos];
-                    if (pt >= 0) val += xout[(long long)pt * k + j];
+        link[q] = -1;
+        link2[q] = -1;
+        lcr[q] = -1;
+        lce[q] = -1;
+        int v = perm[pos];
+        vid[q] = v;
+        if (UP) {
+            if (act && v >= 0) val = yin[(long long)v * k + j];
+            int c0 = lc_ptr[pos], c1 = lc_ptr[pos + 1];
+            if (c1 > c0) link[q] = lc_pos[c0];
+            if (c1 > c0 + 1) link2[q] = lc_pos[c0 + 1];
+            if (c1 > c0 + 2) {
+                lcr[q] = c0 + 2;
+                lce[q] = c1;
+            }
+        } else {
+            if (act) val = F[pos * k + j] * rpw[pos];
+            if (fl & SEG_TOP) link[q] = ptop[pos];
+        }
+        vals[q] = val;
+    }
+
+    // cross-level dependencies (tiles of light children / of path parents)
+    {
+        int d0 = dep_ptr[gt], d1 = dep_ptr[gt + 1];
+        int bad = 0;
+        for (int d = d0 + tid; d < d1; d += kThreads) {
+            const unsigned *f = &done[dep[d]];
+            long long spin = 0;
+            while (ld_agent_u32(f) != epoch) {
+                if (++spin > kSpinLimit) {
+                    bad = 1;
+                    break;
                 }
+                __builtin_amdgcn_s_sleep(1);
             }
         }
+        if (bad) atomicOr(devflags, DEVERR_SPIN);
+    }
+    __syncthreads();
+
+    // the single dependent hop, then the run-local inclusive segmented scan
+    bool pre[NPR];
+    bool seen = false;
+    T acc = 0;
+#pragma unroll
+    for (int q = 0; q < NPR; q++) {
+        T val = vals[q];
+        if (act) {
+            if (UP) {
+                if (link[q] >= 0) val += ld_agent(&F[(long long)link[q] * k + j]);
+                if (link2[q] >= 0) val += ld_agent(&F[(long long)link2[q] * k + j]);
+                for (int c = lcr[q]; c >= 0 && c < lce[q]; c++) val += ld_agent(&F[(long long)lc_pos[c] * k + j]);
+            } else {
+                if (link[q] >= 0) val += ld_agent(&xout[(long long)link[q] * k + j]);
+            }
+        }
+        bool start = UP ? (fls[q] & SEG_BOT) : (fls[q] & SEG_TOP);
         if (start) {
             acc = 0;
             seen = true;
@@ -251,35 +352,30 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
         if (j == 0) st_agent_i32(&hs[gt], any);
         wait_mem();
         if (j == 0) st_agent_u32(&status[gt], epoch);
-        // carry-in from predecessors (only needed when the first element is not a start)
         uint8_t f0 = flags[p0 + (UP ? (TN - 1) : 0)];
         bool first_start = UP ? (f0 & SEG_BOT) : (f0 & SEG_TOP);
         T cin = 0;
         if (!first_start) {
             int cnt = 0;
-            int bad = 0;
-            for (int back = 1; back <= lt + 1 && back <= ntiles; back++) {
-                int plt = UP ? (lt + back) : (lt - back);
-                if (plt < 0 || plt >= ntiles) {
-                    bad = 1;
-                    break;
-                }
-                long long pg = tile_base + plt;
+            int bad = 1;  // cleared when a tile holding a segment start is reached
+            const int npred = UP ? (ntiles - 1 - lt) : lt;  // tiles before this one in scan order
+            for (int back = 1; back <= npred; back++) {
+                long long pg = (long long)lvl_first + (UP ? (lt + back) : (lt - back));
                 long long spin = 0;
                 while (ld_agent_u32(&status[pg]) != epoch) {
-                    if (++spin > kSpinLimit) {
-                        bad = 1;
-                        break;
-                    }
+                    if (++spin > kSpinLimit) break;
                     __builtin_amdgcn_s_sleep(1);
                 }
-                if (bad) break;
+                if (spin > kSpinLimit) break;
                 cnt = back;
-                if (ld_agent_i32(&hs[pg])) break;
+                if (ld_agent_i32(&hs[pg])) {
+                    bad = 0;
+                    break;
+                }
             }
             if (bad && j == 0) atomicOr(devflags, DEVERR_SPIN);
             for (int back = cnt; back >= 1; back--) {
-                long long pg = tile_base + (UP ? (lt + back) : (lt - back));
+                long long pg = (long long)lvl_first + (UP ? (lt + back) : (lt - back));
                 cin += ld_agent(&agg[pg * KP + j]);
             }
         }
@@ -296,17 +392,25 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
         long long pos = p0 + (UP ? (TN - 1 - sidx) : sidx);
         T out = pre[q] ? vals[q] : (T)(rc + vals[q]);
         if (UP) {
-            if (act) F[pos * k + j] = out;
+            if (act) {
+                if (fls[q] & SEG_TOP) st_agent(&F[pos * k + j], out);  // read by the parent's tile
+                else F[pos * k + j] = out;
+            }
         } else {
-            int v = perm[pos];
+            int v = vid[q];
             if (v >= 0 && act) {
-                xout[(long long)v * k + j] = out;
+                st_agent(&xout[(long long)v * k + j], out);  // may be read as a path parent's potential
                 if (rdot) dacc += (double)rdot[(long long)v * k + j] * (double)out;
                 double ao = fabs((double)out);
                 mx = ao > mx ? ao : mx;
             }
         }
     }
+    // completion stamp: all of this tile's stores are done before it is published
+    wait_mem();
+    __syncthreads();
+    if (tid == 0) st_agent_u32(&done[gt], epoch);
+
     if (!UP) {
         if (dot_part) {
             s_red[r][j] = dacc;
@@ -330,6 +434,16 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
                 if (m2 > 0.0) atomicMax(absmax, (unsigned long long)__double_as_longlong(m2));
             }
         }
+    }
+}
+
+// start of a solve: reset the sweep tickets and advance the device-side epoch by
+// two (one per sweep), so stamps of earlier solves never match
+__global__ void k_solve_begin(int *__restrict__ tickets, unsigned *__restrict__ epoch) {
+    if (threadIdx.x == 0) {
+        tickets[0] = 0;
+        tickets[1] = 0;
+        epoch[0] += 2u;
     }
 }
 
@@ -428,105 +542,7 @@ __global__ void k_lambda_min(long long n, const double *__restrict__ degG, const
     }
 }
 
-// ------------------------------------------------------------ PCG pieces
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_axpy2(long long n, int k, const double *__restrict__ alpha,
-                                                    const T *__restrict__ p, const T *__restrict__ q,
-                                                    T *__restrict__ x, T *__restrict__ r, double *__restrict__ part) {
-    constexpr int G = kThreads / KP;
-    constexpr int RPB = G * kRowsPerGroup;
-    __shared__ double sh[G][KP];
-    int g = threadIdx.x / KP, j = threadIdx.x % KP;
-    double acc = 0.0;
-    if (j < k) {
-        T a = (T)alpha[j];
-        long long r0 = (long long)blockIdx.x * RPB;
-        for (int i = g; i < RPB; i += G) {
-            long long v = r0 + i;
-            if (v >= n) break;
-            long long o = v * k + j;
-            x[o] += a * p[o];
-            T rn = r[o] - a * q[o];
-            r[o] = rn;
-            acc += (double)rn * (double)rn;
-        }
-    }
-    sh[g][j] = acc;
-    __syncthreads();
-    if (g == 0) {
-        double t = 0.0;
-        for (int q2 = 0; q2 < G; q2++) t += sh[q2][j];
-        part[(long long)blockIdx.x * KP + j] = t;
-    }
-}
-
-template <typename T>
-__global__ void k_xpby(long long nk, int k, const double *__restrict__ beta, const T *__restrict__ z,
-                       T *__restrict__ p) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (long long)gridDim.x * blockDim.x) {
-        int j = (int)(i % k);
-        p[i] = z[i] + (T)beta[j] * p[i];
-    }
-}
-
-template <typename T>
-__global__ void k_copy(long long nk, const T *__restrict__ a, T *__restrict__ b) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (long long)gridDim.x * blockDim.x)
-        b[i] = a[i];
-}
-
-// alpha_j = rz_j / (p_j' L_P p_j) for active vectors, 0 otherwise
-__global__ void k_pcg_alpha(double *__restrict__ red, int *__restrict__ active, int k) {
-    int j = threadIdx.x;
-    if (j >= k) return;
-    double pq = red[RED_PQ * kMaxK + j], rz = red[RED_RZ * kMaxK + j];
-    double a = 0.0;
-    if (active[j]) {
-        if (pq > 0.0 && rz > 0.0) a = rz / pq;
-        else active[j] = 0;
-    }
-    red[RED_ALPHA * kMaxK + j] = a;
-}
-// deactivate converged vectors; count the active ones
-__global__ void k_pcg_check(double *__restrict__ red, int *__restrict__ active, int k, double tol2) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    int j = threadIdx.x;
-    if (j < k && active[j]) {
-        double rr = red[RED_RR * kMaxK + j], rr0 = red[RED_RR0 * kMaxK + j];
-        if (!(rr > tol2 * rr0)) active[j] = 0;
-        else atomicAdd(&cnt, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) active[kMaxK - 1] = cnt;
-}
-__global__ void k_pcg_beta(double *__restrict__ red, const int *__restrict__ active, int k) {
-    int j = threadIdx.x;
-    if (j >= k) return;
-    double rzn = red[RED_RZN * kMaxK + j], rz = red[RED_RZ * kMaxK + j];
-    double b = 0.0;
-    if (active[j] && rz > 0.0) b = rzn / rz;
-    red[RED_BETA * kMaxK + j] = b;
-    red[RED_RZ * kMaxK + j] = rzn;
-}
-__global__ void k_pcg_start(const double *__restrict__ red_rn, double *__restrict__ red, int *__restrict__ active,
-                            int k) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    int j = threadIdx.x;
-    if (j < kMaxK - 1) active[j] = 0;
-    if (j < k) {
-        double rr0 = red_rn[j];
-        red[RED_RR0 * kMaxK + j] = rr0;
-        active[j] = rr0 > 0.0 ? 1 : 0;
-        if (rr0 > 0.0) atomicAdd(&cnt, 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) active[kMaxK - 1] = cnt;
-}
-
+// ------------------------------------------------------------ FP64 refinement
 // r = b - L_P x in FP64 (difference form), grounded at root; r32 = r rounded to T
 template <typename T, int KP>
 __global__ __launch_bounds__(kThreads) void k_resid64(long long n, int k, const int *__restrict__ prow,
@@ -642,13 +658,18 @@ __global__ void k_absmax(long long nk, const T *__restrict__ x, unsigned long lo
     }
 }
 
-inline int grid_nk(long long nk) { return (int)std::min<long long>(std::max<long long>(1, (nk + 255) / 256), 8192); }
 
 }  // namespace
 
 // ============================================================= host side
 
-static int lap_blocks(const Dims &d) { return div_up(d.n, (kThreads / d.kp) * kRowsPerGroup); }
+static int lap_rows_per_block(int kp) {
+    int r = 0;
+    KP_DISPATCH(kp, { r = LapShape<KP>::RPB; });
+    return r;
+}
+static int lap_blocks(const Dims &d) { return div_up(d.n, lap_rows_per_block(d.kp)); }
+
 static int score_blocks(const Dims &d) { return div_up(d.m, (kThreads / d.kp) * kEdgesPerGroup); }
 static int gauss_blocks(const Dims &d) {
     return (int)std::min<long long>(kGaussBlocksMax, div_up(d.n, kThreads / d.kp));
@@ -673,9 +694,13 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
     v.dx = a.take<T>(nk);
     v.x64 = a.take<double>(nk);
     v.r64 = nullptr;
-    long long parts = std::max<long long>({(long long)lap_blocks(d) + 8, d.ntiles, 2ll * score_blocks(d),
+    long long parts = std::max<long long>({(long long)lap_blocks(d) + 8, (long long)vec_blocks(d) + 8, d.ntiles, 2ll * score_blocks(d),
                                            (long long)gauss_blocks(d)});
     v.part = a.take<double>(parts * d.kp + 64);
+    v.part2 = a.take<double>(64 * d.kp + 64);
+    v.small = a.take<double>(9 * d.kp * d.kp + 64);  // S_SLOTS = 8 matrices
+    v.smallT = a.take<T>(4 * d.kp * d.kp + 64);
+    v.gpart = a.take<double>((long long)gram_blocks(d.kp) * 4 * d.kp * d.kp);
     v.red = a.take<double>(RED_SLOTS * kMaxK);
     v.active = a.take<int>(kMaxK);
     v.u64s = a.take<unsigned long long>(U_SLOTS);
@@ -685,10 +710,11 @@ template <typename T>
 void start_vectors(const Dims &d, uint64_t seed, int pass, T *out, Vecs<T> &v, hipStream_t s) {
     int nb = gauss_blocks(d);
     double *mean = v.red + RED_MEAN * kMaxK;
+    ProfScope ps(PK_START, (double)d.n * d.k * sizeof(T), s);
     KP_DISPATCH(d.kp, {
         hipLaunchKernelGGL(k_gauss_sum<KP>, dim3(nb), dim3(kThreads), 0, s, d.n, d.k, (unsigned long long)seed, pass,
                            v.part);
-        hipLaunchKernelGGL(k_col_sum<KP>, dim3(1), dim3(kThreads), 0, s, v.part, nb, KP, 0, 1.0 / (double)d.n, mean);
+        hipLaunchKernelGGL(k_col_sum<KP>, dim3(1), dim3(kColThreads), 0, s, v.part, nb, KP, 0, 1.0 / (double)d.n, mean);
         hipLaunchKernelGGL((k_gauss_write<T, KP>), dim3(nb), dim3(kThreads), 0, s, d.n, d.k, (unsigned long long)seed,
                            pass, mean, out);
     });
@@ -699,6 +725,10 @@ template <typename T>
 void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const T *x, T *y, int root,
                const unsigned long long *scale_from, double *dot_part, hipStream_t s) {
     int nb = lap_blocks(d);
+    ProfScope ps(root < 0 ? PK_SPMM_G : PK_SPMM_P,
+                 4.0 * (d.n + 1) + (double)(root < 0 ? 2 * d.m : d.p_nnz) * (4 + sizeof(T)) +
+                     2.0 * d.n * d.k * sizeof(T),
+                 s);
     KP_DISPATCH(d.kp, {
         hipLaunchKernelGGL((k_lap<T, KP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col, val, x, y,
                            root, scale_from, dot_part, nb);
@@ -709,28 +739,17 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
 template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s) {
-    fill_i32(t.tickets, 2 * kMaxLevels, 0, s);
-    if (dot_part) fill_f64(dot_part, (t.N / d.TN) * d.kp, 0.0, s);
-    unsigned e_up = ++t.epoch;
-    unsigned e_dn = ++t.epoch;
+    ProfScope ps(PK_TREE, 4.0 * d.n * d.k * sizeof(T) + 21.0 * t.N, s);
+    const int nt = (int)t.ntiles_used;
+    hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(64), 0, s, t.tickets, t.epoch_dev);
     KP_DISPATCH(d.kp, {
-        for (int l = t.nlev - 1; l >= 0; l--) {
-            long long lp0 = t.lvl_start[l];
-            int nt = (int)((t.lvl_start[l + 1] - lp0) / d.TN);
-            if (nt == 0) continue;
-            hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nt), dim3(kThreads), 0, s, lp0, nt, lp0 / d.TN, d.k, t.perm,
-                               t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status, e_up,
-                               t.tickets + 2 * l, t.devflags, (const T *)nullptr, (double *)nullptr,
-                               (unsigned long long *)nullptr);
-        }
-        for (int l = 0; l < t.nlev; l++) {
-            long long lp0 = t.lvl_start[l];
-            int nt = (int)((t.lvl_start[l + 1] - lp0) / d.TN);
-            if (nt == 0) continue;
-            hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nt), dim3(kThreads), 0, s, lp0, nt, lp0 / d.TN, d.k,
-                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status,
-                               e_dn, t.tickets + 2 * l + 1, t.devflags, rdot, dot_part, absmax);
-        }
+        hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nt), dim3(kThreads), 0, s, t.nlev, t.lvl_tile, d.k, t.perm,
+                           t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status, t.done,
+                           t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
+                           (double *)nullptr, (unsigned long long *)nullptr);
+        hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nt), dim3(kThreads), 0, s, t.nlev, t.lvl_tile, d.k, t.perm,
+                           t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status, t.done,
+                           t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part, absmax);
     });
     GR_CHECK_LAUNCH();
 }
@@ -742,10 +761,19 @@ void absmax_of(const Dims &d, const T *x, unsigned long long *slot, hipStream_t 
     GR_CHECK_LAUNCH();
 }
 
+// Fixed-order column sums of per-block partials: one stage up to 2048 partials,
+// else 64-block first stage into Vecs::part2, then one block.
 template <typename T>
-static void col_sum(const Dims &d, const double *part, int nblk, int stride, int offset, double *out, hipStream_t s) {
+void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride, int offset, double *out,
+                    hipStream_t s) {
     KP_DISPATCH(d.kp, {
-        hipLaunchKernelGGL(k_col_sum<KP>, dim3(1), dim3(kThreads), 0, s, part, nblk, stride, offset, 1.0, out);
+        if (nblk <= 2048) {
+            hipLaunchKernelGGL(k_col_sum<KP>, dim3(1), dim3(kColThreads), 0, s, part, nblk, stride, offset, 1.0, out);
+        } else {
+            hipLaunchKernelGGL(k_col_sum<KP>, dim3(64), dim3(kColThreads), 0, s, part, nblk, stride, offset, 1.0,
+                               v.part2);
+            hipLaunchKernelGGL(k_col_sum<KP>, dim3(1), dim3(kColThreads), 0, s, v.part2, 64, KP, 0, 1.0, out);
+        }
     });
     GR_CHECK_LAUNCH();
 }
@@ -756,14 +784,15 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     const long long nk = d.n * d.k;
     const int root = 0;
     const int nbl = lap_blocks(d);
+    const int nbv = vec_blocks(d);
     double *red = v.red;
     double *bn = red + RED_BN * kMaxK, *rn = red + RED_RN * kMaxK;
     // ||b|| per vector (grounded rows)
     KP_DISPATCH(d.kp, {
-        hipLaunchKernelGGL((k_norm2<T, KP>), dim3(nbl), dim3(kThreads), 0, s, d.n, d.k, b, root, v.part);
+        hipLaunchKernelGGL((k_norm2<T, KP>), dim3(nbv), dim3(kThreads), 0, s, d.n, d.k, b, root, v.part);
     });
     GR_CHECK_LAUNCH();
-    col_sum<T>(d, v.part, nbl, d.kp, 0, bn, s);
+    col_sum<T>(d, v, v.part, nbv, d.kp, 0, bn, s);
     fill_f64(v.x64, nk, 0.0, s);
     std::vector<double> hb(2 * kMaxK);
     const double rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
@@ -771,12 +800,16 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     const int max_outer = o.pcg_max_outer > 0 ? o.pcg_max_outer : 6;
     const int max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
     for (int outer = 0;; outer++) {
-        KP_DISPATCH(d.kp, {
-            hipLaunchKernelGGL((k_resid64<T, KP>), dim3(xcd_grid(nbl)), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol,
-                               t.pval64, b, v.x64, v.r, root, v.part, nbl);
-        });
+        {
+            ProfScope ps(PK_RESID64,
+                         4.0 * (d.n + 1) + 12.0 * d.p_nnz + (double)d.n * d.k * (8 + 2 * sizeof(T)), s);
+            KP_DISPATCH(d.kp, {
+                hipLaunchKernelGGL((k_resid64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow,
+                                   t.pcol, t.pval64, b, v.x64, v.r, root, v.part, nbv);
+            });
+        }
         GR_CHECK_LAUNCH();
-        col_sum<T>(d, v.part, nbl, d.kp, 0, rn, s);
+        col_sum<T>(d, v, v.part, nbv, d.kp, 0, rn, s);
         GR_HIP(hipMemcpyAsync(hb.data(), bn, 2 * kMaxK * sizeof(double), hipMemcpyDeviceToHost, s));
         GR_HIP(hipStreamSynchronize(s));
         double worst = 0.0;
@@ -788,39 +821,8 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
         info.resid64 = worst;
         info.outer = outer;
         if (worst <= rtol || outer >= max_outer) break;
-        // inner PCG on the residual: dx = L_P^+ r, r and dx updated in place
-        fill_f64(red + RED_RZ * kMaxK, kMaxK, 0.0, s);
-        hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(64), 0, s, rn, red, v.active, d.k);
-        GR_CHECK_LAUNCH();
-        fill_T(v.dx, nk, (T)0, s);
-        tree_solve<T>(t, v, d, v.r, v.z, v.r, v.part, nullptr, s);
-        col_sum<T>(d, v.part, (int)(t.N / d.TN), d.kp, 0, red + RED_RZ * kMaxK, s);
-        hipLaunchKernelGGL(k_copy<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.z, v.p);
-        GR_CHECK_LAUNCH();
-        long long it = 0;
-        for (; it < max_it;) {
-            it++;
-            lap_apply<T>(d, t.prow, t.pcol, v.pval, v.p, v.q, root, nullptr, v.part, s);
-            col_sum<T>(d, v.part, nbl, d.kp, 0, red + RED_PQ * kMaxK, s);
-            hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(64), 0, s, red, v.active, d.k);
-            KP_DISPATCH(d.kp, {
-                hipLaunchKernelGGL((k_axpy2<T, KP>), dim3(nbl), dim3(kThreads), 0, s, d.n, d.k,
-                                   red + RED_ALPHA * kMaxK, v.p, v.q, v.dx, v.r, v.part);
-            });
-            GR_CHECK_LAUNCH();
-            col_sum<T>(d, v.part, nbl, d.kp, 0, red + RED_RR * kMaxK, s);
-            hipLaunchKernelGGL(k_pcg_check, dim3(1), dim3(64), 0, s, red, v.active, d.k, itol * itol);
-            GR_CHECK_LAUNCH();
-            if ((it & 7) == 0 || it == max_it) {
-                if (read_i32(v.active + kMaxK - 1, s) == 0) break;
-            }
-            tree_solve<T>(t, v, d, v.r, v.z, v.r, v.part, nullptr, s);
-            col_sum<T>(d, v.part, (int)(t.N / d.TN), d.kp, 0, red + RED_RZN * kMaxK, s);
-            hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, s, red, v.active, d.k);
-            hipLaunchKernelGGL(k_xpby<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, d.k, red + RED_BETA * kMaxK,
-                               v.z, v.p);
-            GR_CHECK_LAUNCH();
-        }
+        // inner block PCG on the residual: dx ~ L_P^+ r
+        long long it = block_pcg<T>(t, v, d, itol, max_it, s);
         info.iters += it;
         hipLaunchKernelGGL(k_add_dx<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, v.dx);
         GR_CHECK_LAUNCH();
@@ -835,14 +837,13 @@ template <typename T>
 void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStream_t s) {
     int nb = score_blocks(d);
     fill_u32(reinterpret_cast<unsigned *>(v.u64s + U_HMAX), 2, 0u, s);
+    ProfScope ps(PK_SCORE, (double)d.m * (9 + 2 * sizeof(T)) + (double)d.n * d.k * sizeof(T), s);
     KP_DISPATCH(d.kp, {
         hipLaunchKernelGGL((k_score<T, KP>), dim3(nb), dim3(kThreads), 0, s, d.m, d.k, t.src, t.dst, v.wT, t.mask, H,
                            heat, v.part, v.u64s + U_HMAX);
         GR_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_col_sum<KP>, dim3(1), dim3(kThreads), 0, s, v.part, nb, 2 * KP, 0, 1.0,
-                           v.red + RED_NUM * kMaxK);
-        hipLaunchKernelGGL(k_col_sum<KP>, dim3(1), dim3(kThreads), 0, s, v.part, nb, 2 * KP, KP, 1.0,
-                           v.red + RED_DEN * kMaxK);
+        col_sum<T>(d, v, v.part, nb, 2 * KP, 0, v.red + RED_NUM * kMaxK, s);
+        col_sum<T>(d, v, v.part, nb, 2 * KP, KP, v.red + RED_DEN * kMaxK, s);
         hipLaunchKernelGGL(k_lambda_max<KP>, dim3(1), dim3(64), 0, s, v.red, d.k);
     });
     GR_CHECK_LAUNCH();
@@ -880,7 +881,8 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
                                     hipStream_t);                                                                \
     template void score_edges<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, hipStream_t);                  \
     template PassScalars finish_estimates<T>(Topo &, Vecs<T> &, const Dims &, hipStream_t);                      \
-    template void absmax_of<T>(const Dims &, const T *, unsigned long long *, hipStream_t);
+    template void absmax_of<T>(const Dims &, const T *, unsigned long long *, hipStream_t);               \
+    template void col_sum<T>(const Dims &, Vecs<T> &, const double *, int, int, int, double *, hipStream_t);
 INST(float)
 INST(double)
 

@@ -411,6 +411,45 @@ __global__ void k_lc_fill(long long n, const int *__restrict__ tptr, const int *
     }
 }
 
+// Tile dependencies of the dataflow sweeps: a light child c of u links the tile of
+// u (which needs c's subtree current in the up-sweep) and the tile of c (which
+// needs u's potential in the down-sweep).
+__global__ void k_dep_keys(long long n, const int *__restrict__ parent, const int *__restrict__ head,
+                           const int *__restrict__ lp, int TN, int ntile_bits, unsigned long long *__restrict__ kup,
+                           unsigned long long *__restrict__ kdn, int *__restrict__ flag) {
+    GSTRIDE(v, n) {
+        int p = parent[v];
+        bool light = p >= 0 && head[v] == v;
+        flag[v] = light ? 1 : 0;
+        if (light) {
+            unsigned long long a = (unsigned long long)(lp[p] / TN), b = (unsigned long long)(lp[v] / TN);
+            kup[v] = (a << ntile_bits) | b;
+            kdn[v] = (b << ntile_bits) | a;
+        }
+    }
+}
+__global__ void k_dep_compact(long long n, const int *__restrict__ flag, const int *__restrict__ pos,
+                              const unsigned long long *__restrict__ kin, unsigned long long *__restrict__ kout,
+                              int *__restrict__ vout) {
+    GSTRIDE(v, n) if (flag[v]) {
+        kout[pos[v]] = kin[v];
+        vout[pos[v]] = 0;
+    }
+}
+// after sorting: keep the first of equal keys, count per owning tile
+__global__ void k_dep_unique(long long c, const unsigned long long *__restrict__ key, int ntile_bits,
+                             int *__restrict__ keep, int *__restrict__ cnt) {
+    GSTRIDE(i, c) {
+        bool first = i == 0 || key[i] != key[i - 1];
+        keep[i] = first ? 1 : 0;
+        if (first) atomicAdd(&cnt[(int)(key[i] >> ntile_bits)], 1);
+    }
+}
+__global__ void k_dep_fill(long long c, const unsigned long long *__restrict__ key, const int *__restrict__ keep,
+                           const int *__restrict__ kpos, int ntile_bits, int *__restrict__ dep) {
+    GSTRIDE(i, c) if (keep[i]) dep[kpos[i]] = (int)(key[i] & ((1ull << ntile_bits) - 1));
+}
+
 // ------------------------------------------------------------ CSR of L_P
 __global__ void k_p_count(long long n, const int *__restrict__ rowptr, const int *__restrict__ ceid,
                           const uint8_t *__restrict__ mask, int *__restrict__ cnt) {
@@ -462,7 +501,7 @@ __global__ void k_count_mask(long long m, const uint8_t *__restrict__ mask, int 
 
 void plan_topo(Arena &a, const Dims &d, Topo &t, SetupTmp &st) {
     long long n = d.n, m = d.m;
-    long long m2 = std::max<long long>(2 * m, n + 1);
+    long long m2 = std::max<long long>(2 * m, 2 * n + 2);
     t.n = n;
     t.m = m;
     t.rowptr = a.take<int>(n + 1);
@@ -489,8 +528,15 @@ void plan_topo(Arena &a, const Dims &d, Topo &t, SetupTmp &st) {
     t.lc_ptr = a.take<int>(d.Npad + 1);
     t.lc_pos = a.take<int>(n);
     t.status = a.take<unsigned>(d.ntiles);
+    t.done = a.take<unsigned>(d.ntiles);
     t.hs = a.take<int>(d.ntiles);
     t.tickets = a.take<int>(2 * kMaxLevels);
+    t.epoch_dev = a.take<unsigned>(4);
+    t.lvl_tile = a.take<int>(kMaxLevels + 1);
+    t.dep_up_ptr = a.take<int>(d.ntiles + 1);
+    t.dep_dn_ptr = a.take<int>(d.ntiles + 1);
+    t.dep_up = a.take<int>(n);
+    t.dep_dn = a.take<int>(n);
     plan_scan(a, std::max<long long>(m2, d.Npad + 1) + 1, t.scan);
     plan_sort(a, std::max(m, n), t.sort);
     t.greedy_mark = a.take<int>(n);
@@ -712,7 +758,49 @@ void build_tree(Topo &t, Vecs<T> &v, const Dims &d, SetupTmp &st, hipStream_t s)
     hipLaunchKernelGGL(k_lc_fill, dim3(grid_for(n)), dim3(256), 0, s, n, tptr, tcol, t.parent, t.heavy, t.lp, t.lc_ptr,
                        t.lc_pos);
     GR_CHECK_LAUNCH();
-    fill_u32(t.status, (t.N + d.TN - 1) / d.TN + 1, 0u, s);
+    // per-level tile ranges and per-tile dependencies of the dataflow sweeps
+    long long NT = t.N / d.TN;
+    t.ntiles_used = NT;
+    std::vector<int> lt(kMaxLevels + 1, 0);  // lives until the stream synchronizes below
+    {
+        for (int l = 0; l <= nlev; l++) lt[l] = (int)(t.lvl_start[l] / d.TN);
+        GR_HIP(hipMemcpyAsync(t.lvl_tile, lt.data(), (nlev + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+        int bits = 1;
+        while ((1ll << bits) < NT + 1) bits++;
+        unsigned long long *kup = reinterpret_cast<unsigned long long *>(st.a1[0]);  // tcol no longer needed
+        unsigned long long *kdn = reinterpret_cast<unsigned long long *>(st.a1[2]);  // tsrc no longer needed
+        int *flag = st.n1[0], *fpos2 = st.n1[1];
+        hipLaunchKernelGGL(k_dep_keys, dim3(grid_for(n)), dim3(256), 0, s, n, t.parent, t.head, t.lp, d.TN, bits, kup,
+                           kdn, flag);
+        GR_CHECK_LAUNCH();
+        fill_i32(flag + n, 1, 0, s);
+        scan_excl_i32(flag, fpos2, n + 1, total, t.scan, s);
+        int c = read_i32(total, s);
+        for (int dir = 0; dir < 2; dir++) {
+            unsigned long long *kin = dir == 0 ? kup : kdn;
+            int *ptr = dir == 0 ? t.dep_up_ptr : t.dep_dn_ptr;
+            int *dep = dir == 0 ? t.dep_up : t.dep_dn;
+            int *cntv = st.n1[2], *keep = st.a1[4], *kpos = st.a1[5];
+            fill_i32(cntv, NT + 1, 0, s);
+            if (c > 0) {
+                hipLaunchKernelGGL(k_dep_compact, dim3(grid_for(n)), dim3(256), 0, s, n, flag, fpos2, kin, st.ku,
+                                   st.a1[6]);
+                GR_CHECK_LAUNCH();
+                radix_sort_pairs(st.ku, st.a1[6], c, 2 * bits, t.sort, s);
+                hipLaunchKernelGGL(k_dep_unique, dim3(grid_for(c)), dim3(256), 0, s, (long long)c, st.ku, bits, keep,
+                                   cntv);
+                GR_CHECK_LAUNCH();
+                scan_excl_i32(keep, kpos, c, nullptr, t.scan, s);
+                hipLaunchKernelGGL(k_dep_fill, dim3(grid_for(c)), dim3(256), 0, s, (long long)c, st.ku, keep, kpos,
+                                   bits, dep);
+                GR_CHECK_LAUNCH();
+            }
+            scan_excl_i32(cntv, ptr, NT + 1, nullptr, t.scan, s);
+        }
+    }
+    fill_u32(t.status, d.ntiles, 0u, s);
+    fill_u32(t.done, d.ntiles, 0u, s);
+    fill_u32(t.epoch_dev, 4, 0u, s);
     t.epoch = 0;
     GR_HIP(hipStreamSynchronize(s));
 }

@@ -1,0 +1,92 @@
+// Optional per-kernel-family timing with HIP events recorded on the launch stream.
+#pragma once
+#include "common.h"
+
+namespace grass {
+
+enum ProfKind : int {
+    PK_SPMM_G = 0,  // y = L_G x (k_lap over the CSR of G)
+    PK_SPMM_P,      // q = L_P p inside PCG (k_lap over the CSR of P)
+    PK_TREE,        // one grounded tree solve (all up- and down-sweep levels)
+    PK_SCORE,       // edge scoring (k_score)
+    PK_PCG_VEC,     // PCG vector updates (k_axpy2, k_xpby)
+    PK_RESID64,     // FP64 refinement residual (k_resid64)
+    PK_START,       // start vectors
+    PK_SELECT,      // candidate filter, sort and greedy
+    PK_COUNT
+};
+
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    double ms[PK_COUNT] = {};
+    long long launches[PK_COUNT] = {};
+    double bytes[PK_COUNT] = {};
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        GR_HIP(hipEventCreate(&e));
+        return e;
+    }
+    void reset() {
+        for (int i = 0; i < PK_COUNT; i++) ms[i] = 0, launches[i] = 0, bytes[i] = 0;
+    }
+    // after the stream has been synchronized
+    void resolve() {
+        for (auto &r : recs) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                ms[r.kind] += t;
+                launches[r.kind] += 1;
+                bytes[r.kind] += r.bytes;
+            }
+            pool.push_back(r.a);
+            pool.push_back(r.b);
+        }
+        recs.clear();
+    }
+    ~Profiler() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+        for (auto &r : recs) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+    }
+};
+
+// The profiler of the calling context (set by the C-ABI layer for one call).
+extern thread_local Profiler *g_prof;
+
+struct ProfScope {
+    Profiler *p = nullptr;
+    hipStream_t s;
+    int kind;
+    double bytes;
+    hipEvent_t a{};
+    ProfScope(int kind_, double bytes_, hipStream_t s_) : s(s_), kind(kind_), bytes(bytes_) {
+        if (g_prof && g_prof->on) {
+            p = g_prof;
+            a = p->get();
+            GR_HIP(hipEventRecord(a, s));
+        }
+    }
+    ~ProfScope() {
+        if (p) {
+            hipEvent_t b = p->get();
+            if (hipEventRecord(b, s) == hipSuccess) p->recs.push_back({kind, a, b, bytes});
+        }
+    }
+};
+
+}  // namespace grass

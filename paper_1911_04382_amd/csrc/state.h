@@ -20,6 +20,7 @@ struct Dims {
     int TN = 0;          // tree-solve tile, nodes
     long long Npad = 0;  // padded layout length bound
     long long ntiles = 0;
+    long long p_nnz = 0;  // nonzeros of the CSR of L_P (off-diagonal), host copy
 };
 
 inline Dims make_dims(long long n, long long m, int k, int prec) {
@@ -62,9 +63,15 @@ struct Topo {
     int *lc_ptr = nullptr;         // [Npad+1]
     int *lc_pos = nullptr;         // [n]
     // tile scan state
-    unsigned *status = nullptr;    // [ntiles]
+    unsigned *status = nullptr;    // [ntiles] aggregate published (epoch stamp)
+    unsigned *done = nullptr;      // [ntiles] outputs written (epoch stamp)
     int *hs = nullptr;             // [ntiles]
-    int *tickets = nullptr;        // [2*kMaxLevels]
+    int *tickets = nullptr;        // [2*kMaxLevels]: sweep tickets
+    unsigned *epoch_dev = nullptr; // [2]: current sweep epoch (device-side, advanced per solve)
+    int *lvl_tile = nullptr;       // [kMaxLevels+1] first tile of each level (layout order), device
+    int *dep_up_ptr = nullptr, *dep_up = nullptr;  // per-tile up-sweep dependencies (tiles of light children)
+    int *dep_dn_ptr = nullptr, *dep_dn = nullptr;  // per-tile down-sweep dependencies (tiles of path parents)
+    long long ntiles_used = 0;
     unsigned epoch = 0;
     // scratch for setup and selection
     ScanTmp scan;
@@ -91,6 +98,10 @@ struct Vecs {
     double *x64 = nullptr, *r64 = nullptr;  // [n*kp]
     // reductions
     double *part = nullptr;   // [ntiles*kp*2] per-block partials
+    double *part2 = nullptr;  // [64*kp] first-stage column sums
+    double *small = nullptr;  // k x k FP64 matrices of the block PCG
+    T *smallT = nullptr;      // alpha, beta, R^-1 in working precision
+    double *gpart = nullptr;  // [kPersist][2][kp*kp] Gram partials
     double *red = nullptr;    // [16*kMaxK] reduced vectors (num, den, rz, pq, rr, rr0, bnorm, ...)
     int *active = nullptr;    // [kMaxK] PCG column flags + count at [kMaxK-1]
     unsigned long long *u64s = nullptr;  // [8]: heat max bits, lambda_min bits, absmax bits

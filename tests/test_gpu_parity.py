@@ -219,3 +219,79 @@ def test_error_paths(ctx):
     ws = grass.workspace(dg, opts, DEV)
     res = grass.grass_sparsify(ctx, dg, opts, ws=ws)
     assert res.status in (grass.OK, grass.NOT_CONVERGED)
+
+
+# ------------------------------------------------ full-size and larger cases
+FULL_CASES = [
+    ("c2_100cube_k32", lambda: G.config_c2(100), 32, 2),
+    ("c3_2000sq_longrange_k16_t3", lambda: G.config_c3(2000), 16, 3),
+]
+
+
+@pytest.mark.parametrize("case", FULL_CASES, ids=[c[0] for c in FULL_CASES])
+def test_full_size_tree_pass(ctx, case):
+    """The tree pass (pass 0) of the benchmark workloads at their full sizes, in the
+    launch configuration bench.py times, against the oracle's full computation."""
+    name, mk, k, t = case
+    g = mk()
+    say("full-size tree pass:", name, g.n, g.m)
+    dg = grass.to_device(g, DEV)
+    tmask_gpu = grass.grass_spanning_tree(ctx, dg)
+    tmask = O.max_spanning_tree(g)
+    assert np.array_equal(tmask_gpu.cpu().numpy(), tmask)
+    opts = grass.make_opts(k=k, t=t, precision=32, seed=0)
+    heat, st = grass.grass_embed(ctx, dg, tmask_gpu, opts, pass_=0)
+    heat = heat.cpu().numpy().astype(np.float64)
+    ref = O.embed(g, tmask, k=k, t=t, seed=0, pass_=0)
+    off = tmask == 0
+    err, s, r = _norm_err(heat, ref.heat, off)
+    big = off & (r >= 1e-3)
+    rel = (np.abs(s - r) / r)[big].max()
+    say(f"  max normalized err {err:.3e}, max rel err (scores >= 1e-3) {rel:.3e}, "
+        f"lambda_max {st['lambda_max']:.6g} vs {ref.stats['lambda_max']:.6g}")
+    assert err <= 1e-4
+    assert rel <= 1e-3
+    assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
+    assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
+
+
+def test_pcg_pass_medium_mesh(ctx):
+    """A densified subgraph (PCG solves) on a 30^3 ill-conditioned mesh."""
+    g = G.config_c2(30)
+    k = 8
+    say("PCG pass, 30^3 mesh")
+    tmask = O.max_spanning_tree(g)
+    r0 = O.embed(g, tmask, k=k, t=2, seed=0)
+    th = O.theta(100.0, r0.stats["lambda_min"], r0.stats["lambda_max"], 2)
+    P, acc, _ = O.filter_select(g, r0.heat, tmask, th, r0.stats["heat_max"], sim_hops=1, budget=g.n // 100)
+    dg = grass.to_device(g, DEV)
+    opts = grass.make_opts(k=k, t=2, precision=32, seed=0)
+    heat, st = grass.grass_embed(ctx, dg, torch.as_tensor(P).to(DEV), opts, pass_=1)
+    ref = O.embed(g, P, k=k, t=2, seed=0, pass_=1, pcg_rtol=1e-10)
+    off = P == 0
+    err, s, r = _norm_err(heat.cpu().numpy().astype(np.float64), ref.heat, off)
+    say(f"  pcg iters {st['pcg_iters']} (oracle {ref.stats['pcg_iters']}), resid64 {st['pcg_resid64']:.2e}, "
+        f"max score err {err:.3e}")
+    assert st["pcg_resid64"] <= 1e-6
+    assert err <= 1e-4
+    assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
+
+
+@pytest.mark.parametrize("k,prec", [(32, 32), (16, 32), (24, 32), (8, 32), (64, 32), (5, 64), (32, 64)])
+def test_block_gram_kernel_layout(ctx, k, prec):
+    """The Gram kernel of the block PCG (MFMA accumulators for FP32, k in 9..32)
+    against a float64 product of the same inputs, on a ragged row count."""
+    n = 100003
+    say("block Gram", k, prec)
+    rng = np.random.default_rng(k)
+    a = rng.standard_normal((n, k))
+    b = rng.standard_normal((n, k))
+    dt = torch.float64 if prec == 64 else torch.float32
+    ta, tb = torch.tensor(a, dtype=dt, device=DEV), torch.tensor(b, dtype=dt, device=DEV)
+    got = grass.grass_gram(ctx, ta, tb).cpu().numpy()
+    a32 = ta.cpu().numpy().astype(np.float64)
+    b32 = tb.cpu().numpy().astype(np.float64)
+    ref = a32.T @ b32
+    tol = 1e-12 if prec == 64 else 2e-5
+    np.testing.assert_allclose(got, ref, rtol=0, atol=tol * np.abs(a32).max() * np.abs(b32).max() * n ** 0.5 * 10)
+    assert np.abs(got - ref).max() <= 1e-3 * np.abs(ref).max() or prec == 64
