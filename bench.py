@@ -135,8 +135,7 @@ def main():
     ms_per_step = total / args.steps * 1e3
     value = scored / total
     # dominant bandwidth-bound kernel family of the timed region
-    dom = max((k for k in ("spmm_LG", "spmm_LP", "tree_solve", "score", "pcg_vec", "resid64") if prof[k]["launches"]),
-              key=lambda k: prof[k]["ms"])
+    dom = max((k for k, p in prof.items() if p["launches"] and p["alg_bytes"] > 0), key=lambda k: prof[k]["ms"])
     p = prof[dom]
     achieved = p["alg_bytes"] / (p["ms"] * 1e-3) / 1e9
     line = {

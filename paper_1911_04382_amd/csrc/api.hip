@@ -488,14 +488,14 @@ grass_status grass_gram(grass_ctx *ctx, int64_t n, int32_t k, int32_t precision,
         require(precision == 32 || precision == 64, GRASS_ERR_INVALID, "precision must be 32 or 64");
         hipStream_t s = static_cast<hipStream_t>(stream);
         Dims d = make_dims(n, 1, k, precision);
-        size_t need = ((size_t)gram_blocks(d.kp) * d.kp * d.kp + (size_t)d.kp * d.kp + 64) * sizeof(double) + 1024;
+        size_t need = (size_t)bpcg_part_doubles(d) * sizeof(double) + (size_t)bpcg_counters(d) * sizeof(int) + 1024;
         Arena ar = bind_arena(ctx, nullptr, 0, need);
-        double *gpart = ar.take<double>((size_t)gram_blocks(d.kp) * d.kp * d.kp);
-        double *red = ar.take<double>((size_t)d.kp * d.kp);
+        double *part = ar.take<double>((size_t)bpcg_part_doubles(d));
+        int *cnt = ar.take<int>((size_t)bpcg_counters(d));
         if (precision == 64)
-            block_gram<double>(d, static_cast<const double *>(a), static_cast<const double *>(b), gpart, red, out, s);
+            block_gram<double>(d, static_cast<const double *>(a), static_cast<const double *>(b), part, cnt, out, s);
         else
-            block_gram<float>(d, static_cast<const float *>(a), static_cast<const float *>(b), gpart, red, out, s);
+            block_gram<float>(d, static_cast<const float *>(a), static_cast<const float *>(b), part, cnt, out, s);
         GR_HIP(hipStreamSynchronize(s));
         return GRASS_OK;
     });
@@ -509,8 +509,9 @@ grass_status grass_profile_enable(grass_ctx *ctx, int32_t enable) {
 }
 
 int32_t grass_profile_read(const grass_ctx *ctx, grass_kernel_stats *out, int32_t cap) {
-    static const char *names[PK_COUNT] = {"spmm_LG", "spmm_LP", "tree_solve", "score",
-                                          "pcg_vec", "resid64", "start_vectors", "select"};
+    static const char *names[PK_COUNT] = {"spmm_LG",  "spmm_LP",   "tree_up", "tree_down", "score",
+                                          "bspmm",    "r_update",  "gram_QZ", "p_update",  "p_normalize",
+                                          "resid64",  "start_vectors", "select"};
     if (!ctx) return 0;
     int32_t n = 0;
     for (int i = 0; i < PK_COUNT && n < cap; i++) {

@@ -7,8 +7,10 @@
 //   Z = L_T^+ R, beta = -(P'Q)^-1 (Q'Z), P = Z + P beta,
 //   P <- P chol(P'P)^-1  (keeps the block well conditioned; a direction that
 //                          becomes dependent is dropped).
-// The k x k matrices are reduced in a fixed order and factorised in FP64 by one
-// workgroup, so results are deterministic. Compared with k independent CG runs
+// X += P alpha is deferred to the pass that forms the next P (one read of P).
+// The k x k matrices are reduced in a fixed order at the end of the kernel that
+// produces them and factorised in FP64 by its last workgroup, so results are
+// deterministic and each step costs one launch. Compared with k independent CG runs
 // this needs several times fewer iterations: the block space captures the
 // largest generalized eigenvalues of the tree-preconditioned system together.
 #include "embed.h"
@@ -50,16 +52,17 @@ struct Acc<double> {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// Gram accumulator C += a'b over the rows a block holds (lane l of a wave: row
-// l / KP of the wave, column l % KP). For FP32 with KP = 32 or 16 this is one MFMA
-// per 2 (or 4) rows: in that lane layout the A operand of v_mfma_f32_32x32x2f32
-// (lane l holds A[l % 32][l / 32]) is exactly a' and the B operand (lane l holds
-// B[l / 32][l % 32]) is exactly b, so the instruction accumulates a'b. Other
-// widths and FP64 keep per-lane column accumulators fed by shuffles.
-// flush(): fixed-order FP64 sum over the block into out (KP x KP, row-major).
+// ------------------------------------------------------------ Gram accumulators
+// C += a'b over the rows a block holds (lane l of a wave: row l / KP of the wave,
+// column l % KP). For FP32 with KP = 32 or 16 this is one MFMA per 2 (or 4) rows:
+// in that lane layout the A operand of v_mfma_f32_32x32x2f32 (lane l holds
+// A[l % 32][l / 32]) is exactly a' and the B operand (lane l holds B[l / 32][l % 32])
+// is exactly b, so the instruction accumulates a'b. Other widths and FP64 keep
+// per-lane column accumulators fed by shuffles.
+// flush(s, out): fixed-order FP64 sum over the block (through s, KP*KP doubles of
+// LDS) stored to out with agent-scope stores (read by the tail reduction).
 template <typename T, int KP, bool MF = (sizeof(T) == 4 && (KP == 32 || KP == 16))>
 struct BlockGram {
-    static constexpr int LDS = KP * KP;
     using A = typename Acc<T>::type;
     A acc[KP];
     __device__ void zero() {
@@ -75,27 +78,29 @@ struct BlockGram {
         constexpr int G = kThreads / KP;
         const int g = threadIdx.x / KP, j = threadIdx.x % KP;
         __syncthreads();
-        for (int e = threadIdx.x; e < KP * KP; e += kThreads) s[e] = 0.0;
-        __syncthreads();
         for (int gg = 0; gg < G; gg++) {
             if (g == gg)
-                for (int i = 0; i < KP; i++) s[i * KP + j] += (double)acc[i];
+                for (int i = 0; i < KP; i++) s[i * KP + j] = (gg ? s[i * KP + j] : 0.0) + (double)acc[i];
             __syncthreads();
         }
-        for (int e = threadIdx.x; e < KP * KP; e += kThreads) out[e] = s[e];
+        for (int e = threadIdx.x; e < KP * KP; e += kThreads) st_agent(&out[e], s[e]);
         __syncthreads();
     }
 };
-template <int KP>
-__device__ void flush_waves(double *s, double *__restrict__ out) {
+// one wave's MFMA accumulator into s (wave order fixes the sum order)
+template <int KP, typename F>
+__device__ __forceinline__ void flush_mfma(double *s, double *__restrict__ out, F &&put) {
+    const int w = threadIdx.x >> 6;
     __syncthreads();
-    for (int e = threadIdx.x; e < KP * KP; e += kThreads)
-        out[e] = ((s[e] + s[KP * KP + e]) + s[2 * KP * KP + e]) + s[3 * KP * KP + e];
+    for (int ww = 0; ww < kThreads / 64; ww++) {
+        if (w == ww) put(s, ww == 0);
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < KP * KP; e += kThreads) st_agent(&out[e], s[e]);
     __syncthreads();
 }
 template <typename T>
 struct BlockGram<T, 32, true> {
-    static constexpr int LDS = 4 * 32 * 32;
     floatx16 c;
     __device__ void zero() {
 #pragma unroll
@@ -104,17 +109,18 @@ struct BlockGram<T, 32, true> {
     __device__ void add(float a, float b) { c = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
     // accumulator layout: lane l, register r -> C[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
     __device__ void flush(double *s, double *__restrict__ out) {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        __syncthreads();
+        flush_mfma<32>(s, out, [&](double *sh, bool first) {
+            const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int r = 0; r < 16; r++)
-            s[w * 1024 + (8 * (r / 4) + 4 * (lane / 32) + (r % 4)) * 32 + (lane % 32)] = (double)c[r];
-        flush_waves<32>(s, out);
+            for (int r = 0; r < 16; r++) {
+                int e = (8 * (r / 4) + 4 * (lane / 32) + (r % 4)) * 32 + (lane % 32);
+                sh[e] = (first ? 0.0 : sh[e]) + (double)c[r];
+            }
+        });
     }
 };
 template <typename T>
 struct BlockGram<T, 16, true> {
-    static constexpr int LDS = 4 * 16 * 16;
     floatx4 c;
     __device__ void zero() {
 #pragma unroll
@@ -123,25 +129,272 @@ struct BlockGram<T, 16, true> {
     __device__ void add(float a, float b) { c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     // accumulator layout: lane l, register r -> C[4 (l / 16) + r][l % 16]
     __device__ void flush(double *s, double *__restrict__ out) {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-        __syncthreads();
+        flush_mfma<16>(s, out, [&](double *sh, bool first) {
+            const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int r = 0; r < 4; r++) s[w * 256 + (4 * (lane / 16) + r) * 16 + (lane % 16)] = (double)c[r];
-        flush_waves<16>(s, out);
+            for (int r = 0; r < 4; r++) {
+                int e = (4 * (lane / 16) + r) * 16 + (lane % 16);
+                sh[e] = (first ? 0.0 : sh[e]) + (double)c[r];
+            }
+        });
     }
 };
 
-// Q = L_P P (grounded at root) and the Gram partials P'Q, P'R of this block.
+// ------------------------------------------------------------- tail reduction
+// A kernel whose block b has stored `width` FP64 partials at part + b * width (with
+// agent-scope stores) finishes its reduction itself: blocks are grouped kFan at a
+// time, the last block of a group to arrive (integer arrival counter) sums the
+// group's items in index order into the next level, and so on until one block
+// holds the total. Sums are in a fixed order whatever the arrival order, so the
+// result is deterministic. Counters are returned to zero by the block that
+// consumes them, so consecutive launches (and graph replays) need no clearing.
+constexpr int kFan = 16;
+
+__host__ __device__ inline long long tail_items(long long nblk) {
+    long long s = nblk;
+    while (nblk > 1) {
+        nblk = (nblk + kFan - 1) / kFan;
+        s += nblk;
+    }
+    return s;
+}
+
+// true in exactly one block, which then holds the total in tot[0, width) (LDS)
+__device__ bool tail_reduce(double *part, int nblk, int width, int *cnt, double *tot) {
+    __shared__ int s_last;
+    int idx = blockIdx.x, nl = nblk;
+    double *lvl = part;
+    double *next = part + (long long)nblk * width;
+    int *c = cnt;
+    wait_mem();
+    __syncthreads();
+    if (nl == 1) {
+        for (int e = threadIdx.x; e < width; e += blockDim.x) tot[e] = ld_agent(&part[e]);
+        __syncthreads();
+        return true;
+    }
+    while (true) {
+        const int grp = idx / kFan, first = grp * kFan, gs = min(kFan, nl - first);
+        const int ng = (nl + kFan - 1) / kFan;
+        if (threadIdx.x == 0) {
+            int old = atomicAdd(&c[grp], 1);
+            s_last = old == gs - 1;
+            if (old == gs - 1) atomicExch(&c[grp], 0);
+        }
+        __syncthreads();
+        if (!s_last) return false;
+        for (int e = threadIdx.x; e < width; e += blockDim.x) {
+            double v[kFan];
+#pragma unroll
+            for (int i = 0; i < kFan; i++) v[i] = i < gs ? ld_agent(&lvl[(long long)(first + i) * width + e]) : 0.0;
+            double a = v[0];
+#pragma unroll
+            for (int i = 1; i < kFan; i++) a += v[i];
+            if (ng == 1)
+                tot[e] = a;
+            else
+                st_agent(&next[(long long)grp * width + e], a);
+        }
+        if (ng == 1) {
+            __syncthreads();
+            return true;
+        }
+        wait_mem();
+        __syncthreads();
+        idx = grp;
+        lvl = next;
+        next += (long long)ng * width;
+        c += ng;
+        nl = ng;
+    }
+}
+
+// ---------------------------------------------------------- small k x k algebra
+// Right-looking Cholesky A = L L' of the k x k SPD matrix A (row-major, leading
+// dimension KP) in LDS, L in the lower triangle. A pivot below 1e-13 times the
+// largest diagonal entry marks its direction dependent: dead[j] = 1 and column j
+// of L becomes e_j, so the solves below return 0 in that direction.
+template <int KP>
+__device__ void chol_lds(double *A, int k, int *dead) {
+    __shared__ double s_tol;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int i = 0; i < k; i++) mx = fmax(mx, A[i * KP + i]);
+        s_tol = mx * 1e-13;
+    }
+    __syncthreads();
+    for (int jj = 0; jj < k; jj++) {
+        if (tid == 0) {
+            double d = A[jj * KP + jj];
+            bool ok = d > s_tol;
+            dead[jj] = ok ? 0 : 1;
+            A[jj * KP + jj] = ok ? sqrt(d) : 1.0;
+        }
+        __syncthreads();
+        const double piv = A[jj * KP + jj];
+        const bool dj = dead[jj] != 0;
+        for (int i = jj + 1 + tid; i < k; i += nt) {
+            A[i * KP + jj] = dj ? 0.0 : A[i * KP + jj] / piv;
+            A[jj * KP + i] = 0.0;
+        }
+        __syncthreads();
+        const int rem = k - jj - 1;
+        for (int e = tid; e < rem * rem; e += nt) {
+            int i = jj + 1 + e / rem, p = jj + 1 + e % rem;
+            if (p <= i) A[i * KP + p] -= A[i * KP + jj] * A[p * KP + jj];
+        }
+        __syncthreads();
+    }
+}
+// L' X = B in place (back substitution, all columns at once); rows of dead
+// directions are 0
+template <int KP>
+__device__ void chol_back_lds(const double *L, int k, const int *dead, double *B) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = k - 1; i >= 0; i--) {
+        if (tid < k) B[i * KP + tid] = dead[i] ? 0.0 : B[i * KP + tid] / L[i * KP + i];
+        __syncthreads();
+        for (int e = tid; e < i * k; e += nt) {
+            int r = e / k, c = e % k;
+            B[r * KP + c] -= L[i * KP + r] * B[i * KP + c];
+        }
+        __syncthreads();
+    }
+}
+// L L' X = B in place
+template <int KP>
+__device__ void chol_solve_lds(const double *L, int k, const int *dead, double *B) {
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = 0; i < k; i++) {
+        if (tid < k) B[i * KP + tid] = dead[i] ? 0.0 : B[i * KP + tid] / L[i * KP + i];
+        __syncthreads();
+        const int rem = k - i - 1;
+        for (int e = tid; e < rem * k; e += nt) {
+            int r = i + 1 + e / k, c = e % k;
+            B[r * KP + c] -= L[r * KP + i] * B[i * KP + c];
+        }
+        __syncthreads();
+    }
+    chol_back_lds<KP>(L, k, dead, B);
+}
+// symmetrise the leading k x k block in place; the rest becomes the identity
+template <int KP>
+__device__ void sym_pad(double *A, int k) {
+    for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) {
+        int r = e / KP, c = e % KP;
+        if (r < c) {
+            double a = (r < k && c < k) ? 0.5 * (A[r * KP + c] + A[c * KP + r]) : 0.0;
+            A[r * KP + c] = a;
+            A[c * KP + r] = a;
+        } else if (r == c && r >= k) {
+            A[e] = 1.0;
+        }
+    }
+    __syncthreads();
+}
+
+// Tail operations of the block PCG (the k x k steps, FP64, one workgroup):
+//   ALPHA (tot = [P'Q | P'R]): L = chol(P'Q) kept for BETA; alpha = (P'Q)^-1 P'R
+//   BETA  (tot = Q'Z):         beta = -(P'Q)^-1 Q'Z
+//   NORM  (tot = P'P):         P'P = R'R, rinv = R^-1, zero columns for directions
+//                              P no longer spans (they leave the search block)
+//   STORE (tot = A'B):         the leading k x k block to vec (row-major, ld k)
+enum TailOp : int { TAIL_STORE = 0, TAIL_ALPHA = 1, TAIL_BETA = 2, TAIL_NORM = 3, TAIL_CHECK = 4 };
+// FP64 slots of Vecs::small (KP*KP doubles each)
+enum : int { S_L = 0, S_DEAD = 1 };
+// working-precision slots of Vecs::smallT (KP*KP each)
+enum : int { T_ALPHA = 0, T_NEGALPHA = 1, T_BETA = 2, T_RINV = 3 };
+
+template <typename T>
+struct Tail {
+    double *part;       // level-0 partials (block b at part + b * width), then the level sums
+    int *cnt;           // arrival counters, zero between launches
+    double *sm;         // FP64 k x k slots
+    T *outT;            // alpha, -alpha, beta, rinv in working precision
+    double *vec;        // CHECK: squared residual norms; STORE: k x k result
+    const double *rr0;  // CHECK: squared norms of the right-hand sides
+    int *count;         // CHECK: number of vectors not yet converged
+    double tol2;
+    int op;
+};
+
+template <typename T, int KP>
+__device__ void tail_small(const Tail<T> &tl, int k, double *tot) {
+    constexpr int KK = KP * KP;
+    __shared__ int dead[KP];
+    const int tid = threadIdx.x, nt = blockDim.x;
+    int *gdead = reinterpret_cast<int *>(tl.sm + S_DEAD * KK);
+    if (tl.op == TAIL_STORE) {
+        for (int e = tid; e < k * k; e += nt) tl.vec[e] = tot[(e / k) * KP + e % k];
+    } else if (tl.op == TAIL_ALPHA) {
+        double *A = tot, *B = tot + KK;
+        sym_pad<KP>(A, k);
+        chol_lds<KP>(A, k, dead);
+        for (int e = tid; e < KK; e += nt) {
+            tl.sm[S_L * KK + e] = A[e];
+            int r = e / KP, c = e % KP;
+            if (r >= k || c >= k) B[e] = 0.0;
+        }
+        if (tid < KP) gdead[tid] = tid < k ? dead[tid] : 1;
+        __syncthreads();
+        chol_solve_lds<KP>(A, k, dead, B);
+        for (int e = tid; e < KK; e += nt) {
+            tl.outT[T_ALPHA * KK + e] = (T)B[e];
+            tl.outT[T_NEGALPHA * KK + e] = (T)(-B[e]);
+        }
+    } else if (tl.op == TAIL_BETA) {
+        double *B = tot, *L = tot + KK;
+        for (int e = tid; e < KK; e += nt) {
+            L[e] = tl.sm[S_L * KK + e];
+            int r = e / KP, c = e % KP;
+            B[e] = (r < k && c < k) ? -B[e] : 0.0;
+        }
+        if (tid < KP) dead[tid] = gdead[tid];
+        __syncthreads();
+        chol_solve_lds<KP>(L, k, dead, B);
+        for (int e = tid; e < KK; e += nt) tl.outT[T_BETA * KK + e] = (T)B[e];
+    } else if (tl.op == TAIL_NORM) {
+        double *A = tot, *B = tot + KK;
+        sym_pad<KP>(A, k);
+        chol_lds<KP>(A, k, dead);
+        for (int e = tid; e < KK; e += nt) {
+            int r = e / KP, c = e % KP;
+            B[e] = (r == c && r < k) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        chol_back_lds<KP>(A, k, dead, B);
+        for (int e = tid; e < KK; e += nt) tl.outT[T_RINV * KK + e] = (T)B[e];
+    }
+}
+// CHECK: tot = squared residual norms
+template <typename T>
+__device__ void tail_check(const Tail<T> &tl, int k, const double *tot) {
+    __shared__ int c;
+    if (threadIdx.x == 0) c = 0;
+    __syncthreads();
+    int j = threadIdx.x;
+    if (j < k) {
+        tl.vec[j] = tot[j];
+        if (tot[j] > tl.tol2 * tl.rr0[j]) atomicAdd(&c, 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *tl.count = c;
+}
+
+// ------------------------------------------------------------------ kernels
+// Q = L_P P (grounded at root) and the Gram partials P'Q, P'R of this block; the
+// last block computes alpha.
 template <typename T, int KP>
 __global__ __launch_bounds__(kThreads) void k_bspmm(long long n, int k, const int *__restrict__ prow,
                                                     const int *__restrict__ pcol, const T *__restrict__ pval,
                                                     const T *__restrict__ P, T *__restrict__ Q,
-                                                    const T *__restrict__ R, int root, double *__restrict__ gpart) {
+                                                    const T *__restrict__ R, int root, Tail<T> tl) {
     constexpr int G = BShape<KP>::G, RPT = BShape<KP>::RPT, CAP = BShape<KP>::CAP;
     __shared__ int s_ptr[RPT + 1];
     __shared__ int s_col[CAP];
     __shared__ T s_val[CAP];
-    __shared__ double s_w[BlockGram<T, KP>::LDS];
+    __shared__ double s_w[2 * KP * KP];
     const int tid = threadIdx.x, g = tid / KP, j = tid % KP;
     const bool act = j < k;
     BlockGram<T, KP> gpq, gpr;
@@ -190,25 +443,23 @@ __global__ __launch_bounds__(kThreads) void k_bspmm(long long n, int k, const in
             gpr.add(pv, rv);
         }
     }
-    double *out = gpart + (long long)blockIdx.x * 2 * KP * KP;
+    constexpr int KK = KP * KP;
+    double *out = tl.part + (long long)blockIdx.x * 2 * KK;
     gpq.flush(s_w, out);
-    gpr.flush(s_w, out + KP * KP);
+    gpr.flush(s_w, out + KK);
+    if (tail_reduce(tl.part, gridDim.x, 2 * KK, tl.cnt, s_w)) tail_small<T, KP>(tl, k, s_w);
 }
 
-// Gram partials of this block: A'B, and with NG = 4 also B'B, C'B and C'C.
-template <typename T, int KP, int NG>
+// Gram partials A'B of this block; the last block runs the tail operation.
+template <typename T, int KP>
 __global__ __launch_bounds__(kThreads) void k_bgram(long long n, int k, const T *__restrict__ Am,
-                                                    const T *__restrict__ Bm, const T *__restrict__ Cm,
-                                                    double *__restrict__ gpart) {
+                                                    const T *__restrict__ Bm, Tail<T> tl) {
     constexpr int G = BShape<KP>::G, RPT = BShape<KP>::RPT;
-    __shared__ double s_w[BlockGram<T, KP>::LDS];
+    __shared__ double s_w[2 * KP * KP];
     const int tid = threadIdx.x, g = tid / KP, j = tid % KP;
     const bool act = j < k;
-    BlockGram<T, KP> g0, g1, g2, g3;
+    BlockGram<T, KP> g0;
     g0.zero();
-    g1.zero();
-    g2.zero();
-    g3.zero();
     long long ntile = (n + RPT - 1) / RPT;
     int t0, t1;
     tile_range(ntile, t0, t1);
@@ -219,31 +470,21 @@ __global__ __launch_bounds__(kThreads) void k_bgram(long long n, int k, const T 
         T av = ok ? Am[v * k + j] : (T)0;
         T bv = ok ? Bm[v * k + j] : (T)0;
         g0.add(av, bv);
-        if (NG == 4) {
-            T cv = ok ? Cm[v * k + j] : (T)0;
-            g1.add(bv, bv);
-            g2.add(cv, bv);
-            g3.add(cv, cv);
-        }
     }
-    double *out = gpart + (long long)blockIdx.x * NG * KP * KP;
-    g0.flush(s_w, out);
-    if (NG == 4) {
-        g1.flush(s_w, out + KP * KP);
-        g2.flush(s_w, out + 2 * KP * KP);
-        g3.flush(s_w, out + 3 * KP * KP);
-    }
+    constexpr int KK = KP * KP;
+    g0.flush(s_w, tl.part + (long long)blockIdx.x * KK);
+    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_small<T, KP>(tl, k, s_w);
 }
 
-// X += P alpha; R -= Q alpha; per-block partial sums of R's squared columns.
+// generic R -= Q alpha; per-block squared column norms of R; the last block counts
+// the vectors that have not converged.
 template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_bupdate(long long n, int k, const T *__restrict__ alpha,
-                                                      const T *__restrict__ P, const T *__restrict__ Q,
-                                                      T *__restrict__ X, T *__restrict__ R,
-                                                      double *__restrict__ part) {
+__global__ __launch_bounds__(kThreads) void k_rupdate(long long n, int k, const T *__restrict__ alpha,
+                                                      const T *__restrict__ Q, T *__restrict__ R, Tail<T> tl) {
     constexpr int G = kThreads / KP;
     constexpr int RPB = G * kRowsPerGroup;
     __shared__ double sh[G][KP];
+    __shared__ double tot[KP];
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;
     const bool act = j < k;
     T acol[KP];
@@ -254,17 +495,12 @@ __global__ __launch_bounds__(kThreads) void k_bupdate(long long n, int k, const 
     for (int i = g; i < RPB; i += G) {
         long long v = r0 + i;
         if (v >= n) break;
-        T pv = act ? P[v * k + j] : (T)0;
         T qv = act ? Q[v * k + j] : (T)0;
-        T sp = 0, sq = 0;
+        T sq = 0;
 #pragma unroll
-        for (int q = 0; q < KP; q++) {
-            sp += __shfl(pv, q, KP) * acol[q];
-            sq += __shfl(qv, q, KP) * acol[q];
-        }
+        for (int q = 0; q < KP; q++) sq += __shfl(qv, q, KP) * acol[q];
         if (act) {
             long long o = v * k + j;
-            X[o] += sp;
             T rn = R[o] - sq;
             R[o] = rn;
             rr += (double)rn * (double)rn;
@@ -275,7 +511,76 @@ __global__ __launch_bounds__(kThreads) void k_bupdate(long long n, int k, const 
     if (g == 0) {
         double t = 0.0;
         for (int q = 0; q < G; q++) t += sh[q][j];
-        part[(long long)blockIdx.x * KP + j] = t;
+        st_agent(&tl.part[(long long)blockIdx.x * KP + j], t);
+    }
+    if (tail_reduce(tl.part, gridDim.x, KP, tl.cnt, tot)) tail_check<T>(tl, k, tot);
+}
+
+// generic: X += P alpha, P_new = Z + P beta (one pass over P) with the Gram
+// partials of P_new; the last block computes rinv.
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_pupdate(long long n, int k, const T *__restrict__ alpha,
+                                                      const T *__restrict__ beta, const T *__restrict__ Z,
+                                                      T *__restrict__ P, T *__restrict__ X, Tail<T> tl) {
+    constexpr int G = BShape<KP>::G, RPT = BShape<KP>::RPT;
+    __shared__ double s_w[2 * KP * KP];
+    const int tid = threadIdx.x, g = tid / KP, j = tid % KP;
+    const bool act = j < k;
+    T bcol[KP], acol[KP];
+#pragma unroll
+    for (int i = 0; i < KP; i++) {
+        bcol[i] = act ? beta[i * KP + j] : (T)0;
+        acol[i] = act ? alpha[i * KP + j] : (T)0;
+    }
+    BlockGram<T, KP> gram;
+    gram.zero();
+    long long ntile = (n + RPT - 1) / RPT;
+    int t0, t1;
+    tile_range(ntile, t0, t1);
+    long long v0 = (long long)t0 * RPT, v1 = min(n, (long long)t1 * RPT);
+    for (long long vb = v0; vb < v1; vb += G) {
+        long long v = vb + g;
+        bool ok = act && v < v1;
+        T pv = ok ? P[v * k + j] : (T)0;
+        T sv = ok ? Z[v * k + j] : (T)0;
+        T xv = ok ? X[v * k + j] : (T)0;
+#pragma unroll
+        for (int q = 0; q < KP; q++) {
+            T pq = __shfl(pv, q, KP);
+            sv += pq * bcol[q];
+            xv += pq * acol[q];
+        }
+        if (ok) {
+            P[v * k + j] = sv;
+            X[v * k + j] = xv;
+        }
+        gram.add(sv, sv);
+    }
+    constexpr int KK = KP * KP;
+    gram.flush(s_w, tl.part + (long long)blockIdx.x * KK);
+    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_small<T, KP>(tl, k, s_w);
+}
+
+// generic Out = (ADD ? C : 0) + In M (Out may alias In or C)
+template <typename T, int KP, bool ADD>
+__global__ __launch_bounds__(kThreads) void k_rowmul(long long n, int k, const T *__restrict__ M, const T *In,
+                                                     const T *C, T *Out) {
+    constexpr int G = kThreads / KP;
+    constexpr int RPB = G * kRowsPerGroup;
+    const int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    const bool act = j < k;
+    T col[KP];
+#pragma unroll
+    for (int i = 0; i < KP; i++) col[i] = act ? M[i * KP + j] : (T)0;
+    long long r0 = (long long)blockIdx.x * RPB;
+    for (int i = g; i < RPB; i += G) {
+        long long v = r0 + i;
+        if (v >= n) break;
+        T pv = act ? In[v * k + j] : (T)0;
+        T sv = (ADD && act) ? C[v * k + j] : (T)0;
+#pragma unroll
+        for (int q = 0; q < KP; q++) sv += __shfl(pv, q, KP) * col[q];
+        if (act) Out[v * k + j] = sv;
     }
 }
 
@@ -358,34 +663,26 @@ __device__ __forceinline__ void mf_store_d(float *__restrict__ X, const typename
     }
 }
 
-// X += P alpha; R -= Q alpha (negalpha = -alpha); per-block partial sums of R's
-// squared columns. One row tile per wave.
+// R -= Q alpha (negalpha = -alpha); per-block squared column norms of R; the last
+// block counts the vectors that have not converged. One row tile per wave.
 template <int KP>
-__global__ __launch_bounds__(kThreads) void k_mf_bupdate(long long n, int k, const float *__restrict__ alpha,
-                                                         const float *__restrict__ negalpha,
-                                                         const float *__restrict__ P, const float *__restrict__ Q,
-                                                         float *__restrict__ X, float *__restrict__ R,
-                                                         double *__restrict__ part) {
+__global__ __launch_bounds__(kThreads) void k_mf_rupdate(long long n, int k, const float *__restrict__ negalpha,
+                                                         const float *__restrict__ Q, float *__restrict__ R,
+                                                         Tail<float> tl) {
     constexpr int ROWS = MF<KP>::ROWS;
     __shared__ float sA[4][ROWS * (KP + 1)];
     __shared__ double sn[4][KP];
+    __shared__ double tot[KP];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    float ba[MF<KP>::NS], bn[MF<KP>::NS];
-    mf_load_b<KP>(alpha, ba);
+    float bn[MF<KP>::NS];
     mf_load_b<KP>(negalpha, bn);
-    // every wave runs the same steps (rows past n are zeros and are not stored), so
-    // block barriers order the LDS tile between its writers and readers
+    // every wave runs the same steps (rows past n are zeros and are not stored)
     const long long v0 = ((long long)blockIdx.x * 4 + w) * ROWS;
-    double rr = 0.0;
-    mf_stage<KP>(sA[w], P, v0, n, k);
-    __syncthreads();
-    auto dx = mf_matmul<KP>(mf_load_d<KP>(X, v0, n, k), sA[w], ba);
-    mf_store_d<KP>(X, dx, v0, n, k);
-    __syncthreads();
     mf_stage<KP>(sA[w], Q, v0, n, k);
     __syncthreads();
     auto dr = mf_matmul<KP>(mf_load_d<KP>(R, v0, n, k), sA[w], bn);
     mf_store_d<KP>(R, dr, v0, n, k);
+    double rr = 0.0;
 #pragma unroll
     for (int r = 0; r < MF<KP>::NR; r++) rr += (double)dr[r] * (double)dr[r];
     // lanes holding the same column: combine in a fixed order
@@ -398,21 +695,26 @@ __global__ __launch_bounds__(kThreads) void k_mf_bupdate(long long n, int k, con
     if (lane < KP) sn[w][lane] = rr;
     __syncthreads();
     if (threadIdx.x < KP)
-        part[(long long)blockIdx.x * KP + threadIdx.x] =
-            ((sn[0][threadIdx.x] + sn[1][threadIdx.x]) + sn[2][threadIdx.x]) + sn[3][threadIdx.x];
+        st_agent(&tl.part[(long long)blockIdx.x * KP + threadIdx.x],
+                 ((sn[0][threadIdx.x] + sn[1][threadIdx.x]) + sn[2][threadIdx.x]) + sn[3][threadIdx.x]);
+    if (tail_reduce(tl.part, gridDim.x, KP, tl.cnt, tot)) tail_check<float>(tl, k, tot);
 }
 
-// P_new = Z + P beta (stored unnormalized) and the Gram partials of P_new.
+// X += P alpha and P_new = Z + P beta from one staged copy of P, the Gram partials
+// of P_new; the last block computes rinv. Persistent: every wave takes the same
+// number of row tiles.
 template <int KP>
-__global__ __launch_bounds__(kThreads) void k_mf_bpupdate(long long n, int k, const float *__restrict__ beta,
-                                                          const float *__restrict__ Z, float *__restrict__ P,
-                                                          double *__restrict__ gpart) {
+__global__ __launch_bounds__(kThreads) void k_mf_pupdate(long long n, int k, const float *__restrict__ alpha,
+                                                         const float *__restrict__ beta, const float *__restrict__ Z,
+                                                         float *__restrict__ P, float *__restrict__ X,
+                                                         Tail<float> tl) {
     constexpr int ROWS = MF<KP>::ROWS;
     __shared__ float sA[4][ROWS * (KP + 1)];
-    __shared__ double s_w[BlockGram<float, KP>::LDS];
+    __shared__ double s_w[2 * KP * KP];
     const int w = threadIdx.x >> 6;
-    float bb[MF<KP>::NS];
+    float bb[MF<KP>::NS], ba[MF<KP>::NS];
     mf_load_b<KP>(beta, bb);
+    mf_load_b<KP>(alpha, ba);
     BlockGram<float, KP> gram;
     gram.zero();
     long long ntile = (n + ROWS - 1) / ROWS;
@@ -425,254 +727,40 @@ __global__ __launch_bounds__(kThreads) void k_mf_bpupdate(long long n, int k, co
         __syncthreads();
         mf_stage<KP>(sA[w], P, v0, n, k);
         __syncthreads();
+        auto dx = mf_matmul<KP>(mf_load_d<KP>(X, v0, n, k), sA[w], ba);
+        mf_store_d<KP>(X, dx, v0, n, k);
         auto d = mf_matmul<KP>(mf_load_d<KP>(Z, v0, n, k), sA[w], bb);
         mf_store_d<KP>(P, d, v0, n, k);
 #pragma unroll
         for (int r = 0; r < MF<KP>::NR; r++) gram.add(d[r], d[r]);
     }
-    gram.flush(s_w, gpart + (long long)blockIdx.x * KP * KP);
+    constexpr int KK = KP * KP;
+    gram.flush(s_w, tl.part + (long long)blockIdx.x * KK);
+    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_small<float, KP>(tl, k, s_w);
 }
 
-// P = P rinv
-template <int KP>
-__global__ __launch_bounds__(kThreads) void k_mf_bnormalize(long long n, int k, const float *__restrict__ rinv,
-                                                            float *__restrict__ P) {
+// Out = (ADD ? C : 0) + In M, one row tile per wave (Out may alias In or C: each
+// wave stages its rows of In before it stores them)
+template <int KP, bool ADD>
+__global__ __launch_bounds__(kThreads) void k_mf_rowmul(long long n, int k, const float *__restrict__ M,
+                                                        const float *In, const float *C, float *Out) {
     constexpr int ROWS = MF<KP>::ROWS;
     __shared__ float sA[4][ROWS * (KP + 1)];
     const int w = threadIdx.x >> 6;
     float b[MF<KP>::NS];
-    mf_load_b<KP>(rinv, b);
+    mf_load_b<KP>(M, b);
     const long long v0 = ((long long)blockIdx.x * 4 + w) * ROWS;
-    mf_stage<KP>(sA[w], P, v0, n, k);
+    mf_stage<KP>(sA[w], In, v0, n, k);
     __syncthreads();
     typename MF<KP>::acc_t z;
+    if (ADD) {
+        z = mf_load_d<KP>(C, v0, n, k);
+    } else {
 #pragma unroll
-    for (int r = 0; r < MF<KP>::NR; r++) z[r] = 0.f;
+        for (int r = 0; r < MF<KP>::NR; r++) z[r] = 0.f;
+    }
     auto d = mf_matmul<KP>(z, sA[w], b);
-    mf_store_d<KP>(P, d, v0, n, k);
-}
-
-// generic: P_new = Z + P beta with its Gram partials (other widths / FP64)
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_bpupdate_g(long long n, int k, const T *__restrict__ beta,
-                                                         const T *__restrict__ Z, T *__restrict__ P,
-                                                         double *__restrict__ gpart) {
-    constexpr int G = BShape<KP>::G, RPT = BShape<KP>::RPT;
-    __shared__ double s_w[BlockGram<T, KP>::LDS];
-    const int tid = threadIdx.x, g = tid / KP, j = tid % KP;
-    const bool act = j < k;
-    T bcol[KP];
-#pragma unroll
-    for (int i = 0; i < KP; i++) bcol[i] = act ? beta[i * KP + j] : (T)0;
-    BlockGram<T, KP> gram;
-    gram.zero();
-    long long ntile = (n + RPT - 1) / RPT;
-    int t0, t1;
-    tile_range(ntile, t0, t1);
-    long long v0 = (long long)t0 * RPT, v1 = min(n, (long long)t1 * RPT);
-    for (long long vb = v0; vb < v1; vb += G) {
-        long long v = vb + g;
-        bool ok = act && v < v1;
-        T pv = ok ? P[v * k + j] : (T)0;
-        T sv = ok ? Z[v * k + j] : (T)0;
-#pragma unroll
-        for (int q = 0; q < KP; q++) sv += __shfl(pv, q, KP) * bcol[q];
-        if (ok) P[v * k + j] = sv;
-        gram.add(sv, sv);
-    }
-    gram.flush(s_w, gpart + (long long)blockIdx.x * KP * KP);
-}
-
-// fixed-order sum over the kPersist blocks of width-wide partials
-__global__ void k_reduce_wide(const double *__restrict__ part, int nblk, int width, double *__restrict__ out) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= width) return;
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    int b = 0;
-    for (; b + 3 < nblk; b += 4) {
-        a0 += part[(long long)b * width + e];
-        a1 += part[(long long)(b + 1) * width + e];
-        a2 += part[(long long)(b + 2) * width + e];
-        a3 += part[(long long)(b + 3) * width + e];
-    }
-    for (; b < nblk; b++) a0 += part[(long long)b * width + e];
-    out[e] = (a0 + a1) + (a2 + a3);
-}
-
-// ---------------------------------------------------------- small k x k algebra
-// In-place Cholesky of the k x k SPD matrix A (row-major, leading dimension KP) in
-// LDS: lower factor L in the lower triangle. A pivot below tol * max diagonal marks
-// its direction dependent: dead[j] = 1, L column j = e_j (solves then give 0 there).
-template <int KP>
-__device__ void chol_lds(double *A, int k, int *dead) {
-    __shared__ double s_tol;
-    if (threadIdx.x == 0) {
-        double mx = 0.0;
-        for (int i = 0; i < k; i++) mx = fmax(mx, A[i * KP + i]);
-        s_tol = mx * 1e-13;
-    }
-    __syncthreads();
-    for (int jj = 0; jj < k; jj++) {
-        if (threadIdx.x == 0) {
-            double d = A[jj * KP + jj];
-            for (int p = 0; p < jj; p++) d -= A[jj * KP + p] * A[jj * KP + p];
-            if (!(d > s_tol)) {
-                dead[jj] = 1;
-                A[jj * KP + jj] = 1.0;
-                for (int p = 0; p < jj; p++) A[jj * KP + p] = 0.0;
-            } else {
-                dead[jj] = 0;
-                A[jj * KP + jj] = sqrt(d);
-            }
-        }
-        __syncthreads();
-        int i = jj + 1 + threadIdx.x;
-        if (i < k) {
-            if (dead[jj]) {
-                A[i * KP + jj] = 0.0;
-            } else {
-                double s = A[i * KP + jj];
-                for (int p = 0; p < jj; p++) s -= A[i * KP + p] * A[jj * KP + p];
-                A[i * KP + jj] = s / A[jj * KP + jj];
-            }
-        }
-        __syncthreads();
-    }
-}
-// Solve L L' X = B for the k columns of B (row-major, ld KP) in place; rows of
-// dead directions are set to 0.
-template <int KP>
-__device__ void chol_solve_lds(const double *L, int k, const int *dead, double *B) {
-    int c = threadIdx.x;
-    if (c < k) {
-        for (int i = 0; i < k; i++) {
-            double s = B[i * KP + c];
-            for (int p = 0; p < i; p++) s -= L[i * KP + p] * B[p * KP + c];
-            B[i * KP + c] = dead[i] ? 0.0 : s / L[i * KP + i];
-        }
-        for (int i = k - 1; i >= 0; i--) {
-            double s = B[i * KP + c];
-            for (int p = i + 1; p < k; p++) s -= L[p * KP + i] * B[p * KP + c];
-            B[i * KP + c] = dead[i] ? 0.0 : s / L[i * KP + i];
-        }
-    }
-    __syncthreads();
-}
-
-// A = L L' (Cholesky in place) and Rinv = (L')^-1, upper triangular, in B; columns
-// of dead directions are zero, so P Rinv has orthonormal live columns and zero
-// columns for directions that P no longer spans.
-template <int KP>
-__device__ void chol_rinv(double *A, double *B, int k, int *dead) {
-    chol_lds<KP>(A, k, dead);
-    for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) B[e] = 0.0;
-    __syncthreads();
-    int c = threadIdx.x;
-    if (c < k && !dead[c]) {
-        // back substitution L' x = e_c; x_i = 0 for i > c
-        for (int i = c; i >= 0; i--) {
-            double s = i == c ? 1.0 : 0.0;
-            for (int p = i + 1; p <= c; p++) s -= A[p * KP + i] * B[p * KP + c];
-            B[i * KP + c] = dead[i] ? 0.0 : s / A[i * KP + i];
-        }
-    }
-    __syncthreads();
-}
-
-enum : int { SM_ALPHA = 0, SM_BETA = 1, SM_NORM = 2 };
-// small-matrix slots (KP*KP doubles each) in Vecs::small
-enum : int { S_PQ = 0, S_PR = 1, S_QZ = 2, S_PP = 3, S_L = 4, S_DEAD = 5, S_SLOTS = 6 };
-
-// op ALPHA: L = chol(P'Q), alpha = (P'Q)^-1 P'R  -> outT[0] = alpha, outT[1] = -alpha
-// op BETA:  beta = -(P'Q)^-1 Q'Z (L from ALPHA)  -> outT[2]
-// op NORM:  P'P = R'R, rinv = R^-1 (upper); dependent directions get a zero
-//           column (they leave the search block)  -> outT[3]
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_bsmall(int op, int k, double *__restrict__ sm, T *__restrict__ outT) {
-    __shared__ double A[KP * KP];
-    __shared__ double B[KP * KP];
-    __shared__ int dead[KP];
-    constexpr int KK = KP * KP;
-    double *gPQ = sm + S_PQ * KK, *gPR = sm + S_PR * KK, *gQZ = sm + S_QZ * KK, *gPP = sm + S_PP * KK;
-    double *gL = sm + S_L * KK;
-    int *gdead = reinterpret_cast<int *>(sm + S_DEAD * KK);
-    const int tid = threadIdx.x;
-    if (op == SM_ALPHA || op == SM_NORM) {
-        const double *src = op == SM_ALPHA ? gPQ : gPP;
-        for (int e = tid; e < KK; e += kThreads) {
-            int r = e / KP, c = e % KP;
-            // symmetrise; rows/columns >= k become the identity
-            A[e] = (r < k && c < k) ? 0.5 * (src[r * KP + c] + src[c * KP + r]) : (r == c ? 1.0 : 0.0);
-        }
-        __syncthreads();
-        if (op == SM_ALPHA) {
-            chol_lds<KP>(A, k, dead);
-            for (int e = tid; e < KK; e += kThreads) {
-                gL[e] = A[e];
-                int r = e / KP, c = e % KP;
-                B[e] = (r < k && c < k) ? gPR[e] : 0.0;
-            }
-            if (tid < KP) gdead[tid] = tid < k ? dead[tid] : 1;
-            __syncthreads();
-            chol_solve_lds<KP>(A, k, dead, B);
-            for (int e = tid; e < KK; e += kThreads) {
-                outT[e] = (T)B[e];
-                outT[KK + e] = (T)(-B[e]);
-            }
-        } else {
-            chol_rinv<KP>(A, B, k, dead);
-            for (int e = tid; e < KK; e += kThreads) outT[3 * KK + e] = (T)B[e];
-        }
-    } else {  // SM_BETA
-        for (int e = tid; e < KK; e += kThreads) {
-            A[e] = gL[e];
-            int r = e / KP, c = e % KP;
-            B[e] = (r < k && c < k) ? -gQZ[e] : 0.0;
-        }
-        if (tid < KP) dead[tid] = gdead[tid];
-        __syncthreads();
-        chol_solve_lds<KP>(A, k, dead, B);
-        for (int e = tid; e < KK; e += kThreads) outT[2 * KK + e] = (T)B[e];
-    }
-}
-
-// generic P = P rinv
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_bnormalize_g(long long n, int k, const T *__restrict__ rinv,
-                                                           T *__restrict__ P) {
-    constexpr int G = kThreads / KP;
-    constexpr int RPB = G * kRowsPerGroup;
-    const int g = threadIdx.x / KP, j = threadIdx.x % KP;
-    const bool act = j < k;
-    T col[KP];
-#pragma unroll
-    for (int i = 0; i < KP; i++) col[i] = act ? rinv[i * KP + j] : (T)0;
-    long long r0 = (long long)blockIdx.x * RPB;
-    for (int i = g; i < RPB; i += G) {
-        long long v = r0 + i;
-        if (v >= n) break;
-        T pv = act ? P[v * k + j] : (T)0;
-        T sv = 0;
-#pragma unroll
-        for (int q = 0; q < KP; q++) sv += __shfl(pv, q, KP) * col[q];
-        if (act) P[v * k + j] = sv;
-    }
-}
-
-// convergence: count vectors with ||r_j||^2 > tol2 * ||r0_j||^2
-__global__ void k_bcheck(const double *__restrict__ rr, const double *__restrict__ rr0, int k, double tol2,
-                         int *__restrict__ out) {
-    __shared__ int cnt;
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    int j = threadIdx.x;
-    if (j < k && rr[j] > tol2 * rr0[j]) atomicAdd(&cnt, 1);
-    __syncthreads();
-    if (threadIdx.x == 0) *out = cnt;
-}
-
-__global__ void k_unpad(const double *__restrict__ in, int kp, int k, double *__restrict__ out) {
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) out[e] = in[(e / k) * kp + (e % k)];
+    mf_store_d<KP>(Out, d, v0, n, k);
 }
 
 template <typename T>
@@ -683,144 +771,157 @@ __global__ void k_copy_vec(long long nk, const T *__restrict__ a, T *__restrict_
 
 }  // namespace
 
+// Scratch of the tail reductions: level-0 partials and level sums (doubles) and
+// arrival counters, for the widest launch of the block PCG.
+static long long tail_grid_max(const Dims &d) {
+    long long mf_rows = d.kp == 16 ? 16 : 32;
+    return std::max<long long>({(long long)gram_blocks(d.kp), (long long)vec_blocks(d), div_up(d.n, 4 * mf_rows)});
+}
+long long bpcg_part_doubles(const Dims &d) {
+    const long long KK = (long long)d.kp * d.kp;
+    long long g = gram_blocks(d.kp), v = tail_grid_max(d);
+    return std::max(tail_items(g) * 2 * KK, tail_items(v) * d.kp) + 64;
+}
+long long bpcg_counters(const Dims &d) { return tail_items(tail_grid_max(d)) + 64; }
+
 template <typename T, int KP>
 struct UseMF {
     static constexpr bool value = sizeof(T) == 4 && (KP == 16 || KP == 32);
 };
+template <int KP>
+static int mf_blocks(const Dims &d) {
+    return div_up(d.n, 4 * MF<KP>::ROWS);
+}
 
-// one dispatch per k-width: the MFMA kernels for FP32 with k in 9..32, else generic
+template <typename T>
+static Tail<T> make_tail(Vecs<T> &v, int op) {
+    Tail<T> tl{};
+    tl.part = v.gpart;
+    tl.cnt = v.tcnt;
+    tl.sm = v.small;
+    tl.outT = v.smallT;
+    tl.op = op;
+    return tl;
+}
+
+// R -= Q alpha and the convergence count
 template <typename T, int KP>
-static void update_xr(const Dims &d, Vecs<T> &v, hipStream_t s) {
-    const int KPP = KP * KP;
+static void launch_rupdate(const Dims &d, Vecs<T> &v, Tail<T> tl, hipStream_t s) {
+    const int KK = KP * KP;
+    ProfScope ps(PK_RUPDATE, 3.0 * d.n * d.k * sizeof(T), s);
     if constexpr (UseMF<T, KP>::value) {
-        int nb = (int)((d.n + 4 * MF<KP>::ROWS - 1) / (4 * MF<KP>::ROWS));
-        hipLaunchKernelGGL((k_mf_bupdate<KP>), dim3(nb), dim3(kThreads), 0, s, d.n, d.k, v.smallT, v.smallT + KPP,
-                           v.p, v.q, v.dx, v.r, v.part);
+        hipLaunchKernelGGL((k_mf_rupdate<KP>), dim3(mf_blocks<KP>(d)), dim3(kThreads), 0, s, d.n, d.k,
+                           v.smallT + T_NEGALPHA * KK, v.q, v.r, tl);
     } else {
-        hipLaunchKernelGGL((k_bupdate<T, KP>), dim3(vec_blocks(d)), dim3(kThreads), 0, s, d.n, d.k, v.smallT, v.p,
-                           v.q, v.dx, v.r, v.part);
+        hipLaunchKernelGGL((k_rupdate<T, KP>), dim3(vec_blocks(d)), dim3(kThreads), 0, s, d.n, d.k,
+                           v.smallT + T_ALPHA * KK, v.q, v.r, tl);
     }
 }
+// X += P alpha, P = Z + P beta and rinv of the new P
 template <typename T, int KP>
-static int update_xr_blocks(const Dims &d) {
-    if constexpr (UseMF<T, KP>::value) return (int)((d.n + 4 * MF<KP>::ROWS - 1) / (4 * MF<KP>::ROWS));
-    return vec_blocks(d);
-}
-template <typename T, int KP>
-static void update_p(const Dims &d, Vecs<T> &v, int ngb, hipStream_t s) {
-    const int KPP = KP * KP;
+static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s) {
+    const int KK = KP * KP;
+    ProfScope ps(PK_PUPDATE, 5.0 * d.n * d.k * sizeof(T), s);
+    Tail<T> tl = make_tail(v, TAIL_NORM);
     if constexpr (UseMF<T, KP>::value)
-        hipLaunchKernelGGL((k_mf_bpupdate<KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, v.smallT + 2 * KPP, v.z,
-                           v.p, v.gpart);
+        hipLaunchKernelGGL((k_mf_pupdate<KP>), dim3(gram_blocks(KP)), dim3(kThreads), 0, s, d.n, d.k,
+                           v.smallT + T_ALPHA * KK, v.smallT + T_BETA * KK, v.z, v.p, v.dx, tl);
     else
-        hipLaunchKernelGGL((k_bpupdate_g<T, KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, v.smallT + 2 * KPP, v.z,
-                           v.p, v.gpart);
+        hipLaunchKernelGGL((k_pupdate<T, KP>), dim3(gram_blocks(KP)), dim3(kThreads), 0, s, d.n, d.k,
+                           v.smallT + T_ALPHA * KK, v.smallT + T_BETA * KK, v.z, v.p, v.dx, tl);
 }
-template <typename T, int KP>
-static void normalize_p(const Dims &d, Vecs<T> &v, hipStream_t s) {
-    const int KPP = KP * KP;
-    if constexpr (UseMF<T, KP>::value) {
-        int nb = (int)((d.n + 4 * MF<KP>::ROWS - 1) / (4 * MF<KP>::ROWS));
-        hipLaunchKernelGGL((k_mf_bnormalize<KP>), dim3(nb), dim3(kThreads), 0, s, d.n, d.k, v.smallT + 3 * KPP, v.p);
-    } else {
-        hipLaunchKernelGGL((k_bnormalize_g<T, KP>), dim3(vec_blocks(d)), dim3(kThreads), 0, s, d.n, d.k,
-                           v.smallT + 3 * KPP, v.p);
-    }
+// Out = (ADD ? C : 0) + In M
+template <typename T, int KP, bool ADD>
+static void launch_rowmul(const Dims &d, const T *M, const T *In, const T *C, T *Out, hipStream_t s) {
+    ProfScope ps(PK_ROWMUL, (ADD ? 3.0 : 2.0) * d.n * d.k * sizeof(T), s);
+    if constexpr (UseMF<T, KP>::value)
+        hipLaunchKernelGGL((k_mf_rowmul<KP, ADD>), dim3(mf_blocks<KP>(d)), dim3(kThreads), 0, s, d.n, d.k, M, In, C,
+                           Out);
+    else
+        hipLaunchKernelGGL((k_rowmul<T, KP, ADD>), dim3(vec_blocks(d)), dim3(kThreads), 0, s, d.n, d.k, M, In, C,
+                           Out);
 }
 
 template <typename T>
 long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it, hipStream_t s) {
     const long long nk = d.n * d.k;
     const int root = 0;
-    const int KPP = d.kp * d.kp;
+    const int KK = d.kp * d.kp;
     const int ngb = gram_blocks(d.kp);
-    double *sm = v.small;
-    double *rr0 = v.red + RED_RN * kMaxK, *rr = v.red + RED_RR * kMaxK;
     int *cnt = v.active + kMaxK - 1;
+    fill_i32(v.tcnt, bpcg_counters(d), 0, s);
     fill_T(v.dx, nk, (T)0, s);
     // P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
     tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
     hipLaunchKernelGGL(k_copy_vec<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.z, v.p);
     KP_DISPATCH(d.kp, {
-        ProfScope ps(PK_PCG_VEC, 3.0 * nk * sizeof(T), s);
-        hipLaunchKernelGGL((k_bgram<T, KP, 1>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, v.p, v.p,
-                           (const T *)nullptr, v.gpart);
-        hipLaunchKernelGGL(k_reduce_wide, dim3(div_up(KPP, 256)), dim3(256), 0, s, v.gpart, ngb, KPP,
-                           sm + S_PP * KPP);
-        hipLaunchKernelGGL((k_bsmall<T, KP>), dim3(1), dim3(kThreads), 0, s, (int)SM_NORM, d.k, sm, v.smallT);
-        normalize_p<T, KP>(d, v, s);
-        GR_CHECK_LAUNCH();
-    });
-    long long it = 0;
-    while (it < max_it) {
-        it++;
-        int nbu = 0;
-        KP_DISPATCH(d.kp, {
-            {
-                ProfScope ps(PK_SPMM_P, 4.0 * (d.n + 1) + 8.0 * d.p_nnz + 3.0 * nk * sizeof(T), s);
-                hipLaunchKernelGGL((k_bspmm<T, KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol,
-                                   v.pval, v.p, v.q, v.r, root, v.gpart);
-            }
-            hipLaunchKernelGGL(k_reduce_wide, dim3(div_up(2 * KPP, 256)), dim3(256), 0, s, v.gpart, ngb, 2 * KPP,
-                               sm + S_PQ * KPP);
-            hipLaunchKernelGGL((k_bsmall<T, KP>), dim3(1), dim3(kThreads), 0, s, (int)SM_ALPHA, d.k, sm, v.smallT);
-            {
-                ProfScope ps(PK_PCG_VEC, 6.0 * nk * sizeof(T), s);
-                update_xr<T, KP>(d, v, s);
-            }
-            nbu = update_xr_blocks<T, KP>(d);
-            GR_CHECK_LAUNCH();
-        });
-        col_sum<T>(d, v, v.part, nbu, d.kp, 0, rr, s);
-        hipLaunchKernelGGL(k_bcheck, dim3(1), dim3(64), 0, s, rr, rr0, d.k, itol * itol, cnt);
-        GR_CHECK_LAUNCH();
-        if ((it & 3) == 0 || it == max_it) {
-            if (read_i32(cnt, s) == 0) break;
+        {
+            ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
+            hipLaunchKernelGGL((k_bgram<T, KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, v.p, v.p,
+                               make_tail(v, TAIL_NORM));
         }
-        tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
+        launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
+    });
+    GR_CHECK_LAUNCH();
+    Tail<T> tcheck = make_tail(v, TAIL_CHECK);
+    tcheck.vec = v.red + RED_RR * kMaxK;
+    tcheck.rr0 = v.red + RED_RN * kMaxK;
+    tcheck.count = cnt;
+    tcheck.tol2 = itol * itol;
+    long long it = 0;
+    while (true) {
+        it++;
+        bool stop = false;
         KP_DISPATCH(d.kp, {
             {
-                ProfScope ps(PK_PCG_VEC, 2.0 * nk * sizeof(T), s);
-                hipLaunchKernelGGL((k_bgram<T, KP, 1>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, v.q, v.z,
-                                   (const T *)nullptr, v.gpart);
+                ProfScope ps(PK_BSPMM, 4.0 * (d.n + 1) + (4.0 + sizeof(T)) * d.p_nnz + 3.0 * nk * sizeof(T), s);
+                hipLaunchKernelGGL((k_bspmm<T, KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol,
+                                   v.pval, v.p, v.q, v.r, root, make_tail(v, TAIL_ALPHA));
             }
-            hipLaunchKernelGGL(k_reduce_wide, dim3(div_up(KPP, 256)), dim3(256), 0, s, v.gpart, ngb, KPP,
-                               sm + S_QZ * KPP);
-            hipLaunchKernelGGL((k_bsmall<T, KP>), dim3(1), dim3(kThreads), 0, s, (int)SM_BETA, d.k, sm, v.smallT);
-            {
-                ProfScope ps(PK_PCG_VEC, 3.0 * nk * sizeof(T), s);
-                update_p<T, KP>(d, v, ngb, s);
+            launch_rupdate<T, KP>(d, v, tcheck, s);
+            GR_CHECK_LAUNCH();
+            if (it >= max_it || (it & 3) == 0) {
+                if (it >= max_it || read_i32(cnt, s) == 0) {
+                    // the last step's X += P alpha
+                    launch_rowmul<T, KP, true>(d, v.smallT + T_ALPHA * KK, v.p, v.dx, v.dx, s);
+                    stop = true;
+                }
             }
-            hipLaunchKernelGGL(k_reduce_wide, dim3(div_up(KPP, 256)), dim3(256), 0, s, v.gpart, ngb, KPP,
-                               sm + S_PP * KPP);
-            hipLaunchKernelGGL((k_bsmall<T, KP>), dim3(1), dim3(kThreads), 0, s, (int)SM_NORM, d.k, sm, v.smallT);
-            {
-                ProfScope ps(PK_PCG_VEC, 2.0 * nk * sizeof(T), s);
-                normalize_p<T, KP>(d, v, s);
+            if (!stop) {
+                tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
+                {
+                    ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
+                    hipLaunchKernelGGL((k_bgram<T, KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, v.q, v.z,
+                                       make_tail(v, TAIL_BETA));
+                }
+                launch_pupdate<T, KP>(d, v, s);
+                launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
             }
             GR_CHECK_LAUNCH();
         });
+        if (stop) break;
     }
     return it;
 }
 
 // Diagnostics: C = A'B (FP64, k x k, row-major ld k) for device n x k blocks,
-// with the Gram kernel of the block PCG.
+// with the Gram kernel of the block PCG; part and cnt as sized by
+// bpcg_part_doubles / bpcg_counters.
 template <typename T>
-void block_gram(const Dims &d, const T *A, const T *B, double *gpart, double *red, double *out, hipStream_t s) {
-    const int KPP = d.kp * d.kp;
+void block_gram(const Dims &d, const T *A, const T *B, double *part, int *cnt, double *out, hipStream_t s) {
+    fill_i32(cnt, bpcg_counters(d), 0, s);
+    Tail<T> tl{};
+    tl.part = part;
+    tl.cnt = cnt;
+    tl.vec = out;
+    tl.op = TAIL_STORE;
     KP_DISPATCH(d.kp, {
-        hipLaunchKernelGGL((k_bgram<T, KP, 1>), dim3(gram_blocks(d.kp)), dim3(kThreads), 0, s, d.n, d.k, A, B,
-                           (const T *)nullptr, gpart);
-        hipLaunchKernelGGL(k_reduce_wide, dim3(div_up(KPP, 256)), dim3(256), 0, s, gpart, gram_blocks(d.kp), KPP,
-                           red);
-        hipLaunchKernelGGL(k_unpad, dim3(1), dim3(256), 0, s, red, KP, d.k, out);
+        hipLaunchKernelGGL((k_bgram<T, KP>), dim3(gram_blocks(d.kp)), dim3(kThreads), 0, s, d.n, d.k, A, B, tl);
     });
     GR_CHECK_LAUNCH();
 }
-template void block_gram<float>(const Dims &, const float *, const float *, double *, double *, double *,
-                                hipStream_t);
-template void block_gram<double>(const Dims &, const double *, const double *, double *, double *, double *,
+template void block_gram<float>(const Dims &, const float *, const float *, double *, int *, double *, hipStream_t);
+template void block_gram<double>(const Dims &, const double *, const double *, double *, int *, double *,
                                  hipStream_t);
 
 template long long block_pcg<float>(Topo &, Vecs<float> &, const Dims &, double, int, hipStream_t);

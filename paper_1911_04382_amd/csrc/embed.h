@@ -67,10 +67,15 @@ void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride
 template <typename T>
 long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it, hipStream_t s);
 
+// Scratch of the block PCG's in-kernel reductions: doubles of Vecs::gpart and
+// counters of Vecs::tcnt.
+long long bpcg_part_doubles(const Dims &d);
+long long bpcg_counters(const Dims &d);
+
 // Diagnostics: C = A'B (k x k, FP64, row-major) with the block-PCG Gram kernel;
-// gpart needs kPersist * kp * kp doubles, red kp * kp.
+// part and cnt sized as above.
 template <typename T>
-void block_gram(const Dims &d, const T *A, const T *B, double *gpart, double *red, double *out, hipStream_t s);
+void block_gram(const Dims &d, const T *A, const T *B, double *part, int *cnt, double *out, hipStream_t s);
 
 // max|x| of an n x k block into the absmax slot
 template <typename T>

@@ -698,9 +698,10 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
                                            (long long)gauss_blocks(d)});
     v.part = a.take<double>(parts * d.kp + 64);
     v.part2 = a.take<double>(64 * d.kp + 64);
-    v.small = a.take<double>(9 * d.kp * d.kp + 64);  // S_SLOTS = 8 matrices
-    v.smallT = a.take<T>(4 * d.kp * d.kp + 64);
-    v.gpart = a.take<double>((long long)gram_blocks(d.kp) * 4 * d.kp * d.kp);
+    v.small = a.take<double>(2 * d.kp * d.kp + 64);  // Cholesky factor, dead flags
+    v.smallT = a.take<T>(4 * d.kp * d.kp + 64);      // alpha, -alpha, beta, R^-1
+    v.gpart = a.take<double>(bpcg_part_doubles(d));
+    v.tcnt = a.take<int>(bpcg_counters(d));
     v.red = a.take<double>(RED_SLOTS * kMaxK);
     v.active = a.take<int>(kMaxK);
     v.u64s = a.take<unsigned long long>(U_SLOTS);
@@ -739,17 +740,26 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
 template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s) {
-    ProfScope ps(PK_TREE, 4.0 * d.n * d.k * sizeof(T) + 21.0 * t.N, s);
     const int nt = (int)t.ntiles_used;
+    const double vbytes = 2.0 * d.n * d.k * sizeof(T);
     hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(64), 0, s, t.tickets, t.epoch_dev);
     KP_DISPATCH(d.kp, {
-        hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nt), dim3(kThreads), 0, s, t.nlev, t.lvl_tile, d.k, t.perm,
-                           t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status, t.done,
-                           t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
-                           (double *)nullptr, (unsigned long long *)nullptr);
-        hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nt), dim3(kThreads), 0, s, t.nlev, t.lvl_tile, d.k, t.perm,
-                           t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status, t.done,
-                           t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part, absmax);
+        {
+            // y in, subtree sums out; per node: flags, perm, light-child pointers
+            ProfScope ps(PK_TREE_UP, vbytes + 13.0 * d.n, s);
+            hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nt), dim3(kThreads), 0, s, t.nlev, t.lvl_tile, d.k,
+                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status,
+                               t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
+                               (double *)nullptr, (unsigned long long *)nullptr);
+        }
+        {
+            // subtree sums in, potentials out; per node: flags, perm, path top, 1/w
+            ProfScope ps(PK_TREE_DOWN, vbytes + (9.0 + sizeof(T)) * d.n, s);
+            hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nt), dim3(kThreads), 0, s, t.nlev, t.lvl_tile, d.k,
+                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status,
+                               t.done, t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part,
+                               absmax);
+        }
     });
     GR_CHECK_LAUNCH();
 }

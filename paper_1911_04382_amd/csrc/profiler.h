@@ -6,10 +6,15 @@ namespace grass {
 
 enum ProfKind : int {
     PK_SPMM_G = 0,  // y = L_G x (k_lap over the CSR of G)
-    PK_SPMM_P,      // q = L_P p inside PCG (k_lap over the CSR of P)
-    PK_TREE,        // one grounded tree solve (all up- and down-sweep levels)
+    PK_SPMM_P,      // y = L_P x (k_lap over the CSR of P)
+    PK_TREE_UP,     // tree solve, leaf-to-root sweep (k_sweep, up)
+    PK_TREE_DOWN,   // tree solve, root-to-leaf sweep (k_sweep, down)
     PK_SCORE,       // edge scoring (k_score)
-    PK_PCG_VEC,     // PCG vector updates (k_axpy2, k_xpby)
+    PK_BSPMM,       // block PCG: Q = L_P P with P'Q, P'R and alpha
+    PK_RUPDATE,     // block PCG: R -= Q alpha and the convergence count
+    PK_BGRAM,       // block PCG: Q'Z and beta (also P'P of the first block)
+    PK_PUPDATE,     // block PCG: X += P alpha, P = Z + P beta, P'P and R^-1
+    PK_ROWMUL,      // block PCG: P = P R^-1 (and the last X += P alpha)
     PK_RESID64,     // FP64 refinement residual (k_resid64)
     PK_START,       // start vectors
     PK_SELECT,      // candidate filter, sort and greedy

@@ -101,7 +101,8 @@ struct Vecs {
     double *part2 = nullptr;  // [64*kp] first-stage column sums
     double *small = nullptr;  // k x k FP64 matrices of the block PCG
     T *smallT = nullptr;      // alpha, beta, R^-1 in working precision
-    double *gpart = nullptr;  // [kPersist][2][kp*kp] Gram partials
+    double *gpart = nullptr;  // block-PCG tail reductions: per-block partials and level sums
+    int *tcnt = nullptr;      // their arrival counters (zero between launches)
     double *red = nullptr;    // [16*kMaxK] reduced vectors (num, den, rz, pq, rr, rr0, bnorm, ...)
     int *active = nullptr;    // [kMaxK] PCG column flags + count at [kMaxK-1]
     unsigned long long *u64s = nullptr;  // [8]: heat max bits, lambda_min bits, absmax bits
