@@ -186,7 +186,10 @@ __device__ bool tail_reduce(double *part, int nblk, int width, int *cnt, double 
         for (int e = threadIdx.x; e < width; e += blockDim.x) {
             double v[kFan];
 #pragma unroll
-            for (int i = 0; i < kFan; i++) v[i] = i < gs ? ld_agent(&lvl[(long long)(first + i) * width + e]) : 0.0;
+            for (int i = 0; i < kFan; i++) {
+                double x = ld_agent(&lvl[(long long)(first + (i < gs ? i : 0)) * width + e]);
+                v[i] = i < gs ? x : 0.0;
+            }
             double a = v[0];
 #pragma unroll
             for (int i = 1; i < kFan; i++) a += v[i];
@@ -417,30 +420,61 @@ __global__ __launch_bounds__(kThreads) void k_bspmm(long long n, int k, const in
                 s_val[i] = pval[base + i];
             }
         __syncthreads();
-        for (int it = 0; it < RPT / G; it++) {  // every lane runs every iteration (MFMA needs the whole wave)
+        // Every lane runs every row step (MFMA needs the whole wave). Loads are
+        // unconditional (clamped index, then a select) so that the rows' own values
+        // and their first two neighbours are all in flight together; further
+        // neighbours (rare in a tree plus a few edges) follow in a loop.
+        constexpr int NIT = RPT / G;
+        T pv[NIT], rv[NIT], x0[NIT], x1[NIT], w0[NIT], w1[NIT];
+        int pp[NIT], pe[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
             int i = g + it * G;
-            bool row = i < nrows;
-            long long v = r0 + i;
-            T pv = (act && row) ? P[v * k + j] : (T)0;
-            T rv = (act && row) ? R[v * k + j] : (T)0;
+            bool ok = act && i < nrows;
+            long long o = ok ? (r0 + i) * k + j : 0;
+            pv[it] = P[o];
+            rv[it] = R[o];
+            pv[it] = ok ? pv[it] : (T)0;
+            rv[it] = ok ? rv[it] : (T)0;
+            int ii = ok ? i : 0;
+            int p0 = s_ptr[ii] - base, p1 = s_ptr[ii + 1] - base;
+            if (!ok) p1 = p0;
+            pp[it] = p0;
+            pe[it] = p1;
+            int c0, c1;
+            if (staged) {
+                c0 = s_col[p0 < p1 ? p0 : 0];
+                c1 = s_col[p0 + 1 < p1 ? p0 + 1 : 0];
+                w0[it] = s_val[p0 < p1 ? p0 : 0];
+                w1[it] = s_val[p0 + 1 < p1 ? p0 + 1 : 0];
+            } else {
+                c0 = pcol[base + (p0 < p1 ? p0 : 0)];
+                c1 = pcol[base + (p0 + 1 < p1 ? p0 + 1 : 0)];
+                w0[it] = pval[base + (p0 < p1 ? p0 : 0)];
+                w1[it] = pval[base + (p0 + 1 < p1 ? p0 + 1 : 0)];
+            }
+            x0[it] = P[p0 < p1 ? (long long)c0 * k + j : 0];
+            x1[it] = P[p0 + 1 < p1 ? (long long)c1 * k + j : 0];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            int i = g + it * G;
+            const int p0 = pp[it], p1 = pe[it];
             T acc = 0;
-            if (act && row) {
-                int p = s_ptr[i] - base, pe = s_ptr[i + 1] - base;
-                if (staged) {
-                    for (; p + 1 < pe; p += 2) {
-                        T x0 = P[(long long)s_col[p] * k + j], x1 = P[(long long)s_col[p + 1] * k + j];
-                        acc += s_val[p] * (pv - x0);
-                        acc += s_val[p + 1] * (pv - x1);
-                    }
-                    for (; p < pe; p++) acc += s_val[p] * (pv - P[(long long)s_col[p] * k + j]);
-                } else {
-                    for (; p < pe; p++) acc += pval[base + p] * (pv - P[(long long)pcol[base + p] * k + j]);
-                }
+            if (p0 < p1) acc += w0[it] * (pv[it] - x0[it]);
+            if (p0 + 1 < p1) acc += w1[it] * (pv[it] - x1[it]);
+            for (int p = p0 + 2; p < p1; p++) {
+                int c = staged ? s_col[p] : pcol[base + p];
+                T w = staged ? s_val[p] : pval[base + p];
+                acc += w * (pv[it] - P[(long long)c * k + j]);
+            }
+            if (act && i < nrows) {
+                long long v = r0 + i;
                 if (v == root) acc = 0;
                 Q[v * k + j] = acc;
             }
-            gpq.add(pv, acc);
-            gpr.add(pv, rv);
+            gpq.add(pv[it], acc);
+            gpr.add(pv[it], rv[it]);
         }
     }
     constexpr int KK = KP * KP;
@@ -464,12 +498,21 @@ __global__ __launch_bounds__(kThreads) void k_bgram(long long n, int k, const T 
     int t0, t1;
     tile_range(ntile, t0, t1);
     long long v0 = (long long)t0 * RPT, v1 = min(n, (long long)t1 * RPT);
-    for (long long vb = v0; vb < v1; vb += G) {  // uniform trip count across the block
-        long long v = vb + g;
-        bool ok = act && v < v1;
-        T av = ok ? Am[v * k + j] : (T)0;
-        T bv = ok ? Bm[v * k + j] : (T)0;
-        g0.add(av, bv);
+    constexpr int U = sizeof(T) == 4 ? 8 : 4;  // rows per lane group in flight
+    for (long long vb = v0; vb < v1; vb += (long long)G * U) {  // uniform trip count across the block
+        T av[U], bv[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            long long v = vb + (long long)u * G + g;
+            bool ok = act && v < v1;
+            long long o = ok ? v * k + j : 0;
+            av[u] = Am[o];
+            bv[u] = Bm[o];
+            av[u] = ok ? av[u] : (T)0;
+            bv[u] = ok ? bv[u] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) g0.add(av[u], bv[u]);
     }
     constexpr int KK = KP * KP;
     g0.flush(s_w, tl.part + (long long)blockIdx.x * KK);
@@ -622,14 +665,34 @@ __device__ __forceinline__ void mf_load_b(const float *__restrict__ M, float (&b
 #pragma unroll
     for (int s2 = 0; s2 < MF<KP>::NS; s2++) b[s2] = M[MF<KP>::kidx(lane, s2) * KP + MF<KP>::dcol(lane)];
 }
-// stage rows [v0, v0 + ROWS) of an n x k block into this wave's LDS tile (zeros outside)
+// Rows [v0, v0 + ROWS) of an n x k block for this wave's LDS tile (zeros outside):
+// mf_fetch issues the loads (unconditional: clamped address, then a select, all in
+// flight together), mf_put writes the tile.
 template <int KP>
-__device__ __forceinline__ void mf_stage(float *sA, const float *__restrict__ X, long long v0, long long n, int k) {
+struct MFTile {
+    static constexpr int NE = MF<KP>::ROWS * KP / 64;
+    float x[NE];
+};
+template <int KP>
+__device__ __forceinline__ void mf_fetch(MFTile<KP> &t, const float *__restrict__ X, long long v0, long long n,
+                                         int k) {
     const int lane = threadIdx.x & 63;
-    for (int e = lane; e < MF<KP>::ROWS * KP; e += 64) {
-        int r = e / KP, c = e % KP;
+#pragma unroll
+    for (int q = 0; q < MFTile<KP>::NE; q++) {
+        int e = lane + 64 * q, r = e / KP, c = e % KP;
         long long v = v0 + r;
-        sA[r * (KP + 1) + c] = (v < n && c < k) ? X[v * k + c] : 0.f;
+        bool ok = v < n && c < k;
+        float x = X[ok ? v * k + c : 0];
+        t.x[q] = ok ? x : 0.f;
+    }
+}
+template <int KP>
+__device__ __forceinline__ void mf_put(float *sA, const MFTile<KP> &t) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < MFTile<KP>::NE; q++) {
+        int e = lane + 64 * q, r = e / KP, c = e % KP;
+        sA[r * (KP + 1) + c] = t.x[q];
     }
 }
 template <int KP>
@@ -640,7 +703,7 @@ __device__ __forceinline__ typename MF<KP>::acc_t mf_matmul(typename MF<KP>::acc
     for (int s2 = 0; s2 < MF<KP>::NS; s2++) acc = MF<KP>::mfma(sA[MF<KP>::arow(lane) * (KP + 1) + MF<KP>::kidx(lane, s2)], b[s2], acc);
     return acc;
 }
-// load / store a tile in the D layout
+// load / store a tile in the D layout (loads unconditional, as in mf_fetch)
 template <int KP>
 __device__ __forceinline__ typename MF<KP>::acc_t mf_load_d(const float *__restrict__ X, long long v0, long long n, int k) {
     const int lane = threadIdx.x & 63, c = MF<KP>::dcol(lane);
@@ -648,7 +711,9 @@ __device__ __forceinline__ typename MF<KP>::acc_t mf_load_d(const float *__restr
 #pragma unroll
     for (int r = 0; r < MF<KP>::NR; r++) {
         long long v = v0 + MF<KP>::drow(lane, r);
-        a[r] = (v < n && c < k) ? X[v * k + c] : 0.f;
+        bool ok = v < n && c < k;
+        float x = X[ok ? v * k + c : 0];
+        a[r] = ok ? x : 0.f;
     }
     return a;
 }
@@ -678,9 +743,12 @@ __global__ __launch_bounds__(kThreads) void k_mf_rupdate(long long n, int k, con
     mf_load_b<KP>(negalpha, bn);
     // every wave runs the same steps (rows past n are zeros and are not stored)
     const long long v0 = ((long long)blockIdx.x * 4 + w) * ROWS;
-    mf_stage<KP>(sA[w], Q, v0, n, k);
+    MFTile<KP> tq;
+    mf_fetch<KP>(tq, Q, v0, n, k);
+    auto cr = mf_load_d<KP>(R, v0, n, k);
+    mf_put<KP>(sA[w], tq);
     __syncthreads();
-    auto dr = mf_matmul<KP>(mf_load_d<KP>(R, v0, n, k), sA[w], bn);
+    auto dr = mf_matmul<KP>(cr, sA[w], bn);
     mf_store_d<KP>(R, dr, v0, n, k);
     double rr = 0.0;
 #pragma unroll
@@ -724,12 +792,16 @@ __global__ __launch_bounds__(kThreads) void k_mf_pupdate(long long n, int k, con
     for (long long it = 0; it < per; it++) {  // same trip count in every wave
         long long tile = t0 + it;
         long long v0 = tile < ntile ? tile * ROWS : n;  // past the end: zeros, nothing stored
+        MFTile<KP> tp;
+        mf_fetch<KP>(tp, P, v0, n, k);
+        auto cx = mf_load_d<KP>(X, v0, n, k);
+        auto cz = mf_load_d<KP>(Z, v0, n, k);
+        __syncthreads();  // the previous tile's reads of sA are done
+        mf_put<KP>(sA[w], tp);
         __syncthreads();
-        mf_stage<KP>(sA[w], P, v0, n, k);
-        __syncthreads();
-        auto dx = mf_matmul<KP>(mf_load_d<KP>(X, v0, n, k), sA[w], ba);
+        auto dx = mf_matmul<KP>(cx, sA[w], ba);
         mf_store_d<KP>(X, dx, v0, n, k);
-        auto d = mf_matmul<KP>(mf_load_d<KP>(Z, v0, n, k), sA[w], bb);
+        auto d = mf_matmul<KP>(cz, sA[w], bb);
         mf_store_d<KP>(P, d, v0, n, k);
 #pragma unroll
         for (int r = 0; r < MF<KP>::NR; r++) gram.add(d[r], d[r]);
@@ -750,8 +822,8 @@ __global__ __launch_bounds__(kThreads) void k_mf_rowmul(long long n, int k, cons
     float b[MF<KP>::NS];
     mf_load_b<KP>(M, b);
     const long long v0 = ((long long)blockIdx.x * 4 + w) * ROWS;
-    mf_stage<KP>(sA[w], In, v0, n, k);
-    __syncthreads();
+    MFTile<KP> ti;
+    mf_fetch<KP>(ti, In, v0, n, k);
     typename MF<KP>::acc_t z;
     if (ADD) {
         z = mf_load_d<KP>(C, v0, n, k);
@@ -759,6 +831,8 @@ __global__ __launch_bounds__(kThreads) void k_mf_rowmul(long long n, int k, cons
 #pragma unroll
         for (int r = 0; r < MF<KP>::NR; r++) z[r] = 0.f;
     }
+    mf_put<KP>(sA[w], ti);
+    __syncthreads();
     auto d = mf_matmul<KP>(z, sA[w], b);
     mf_store_d<KP>(Out, d, v0, n, k);
 }

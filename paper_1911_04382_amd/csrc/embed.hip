@@ -252,7 +252,9 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
     const bool act = j < k;
 
     // Everything that does not depend on other tiles is loaded first, so that the
-    // critical path through the levels keeps a single memory hop per tile.
+    // critical path through the levels keeps a single memory hop per tile. The
+    // loads go in two unconditional rounds (clamped indices, then selects): the
+    // per-position layout data, then what it points to.
     T vals[NPR];
     int link[NPR];     // UP: first light child's position; DOWN: parent of the path top
     int link2[NPR];    // UP: second light child's position (or -1)
@@ -260,41 +262,56 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
     int lce[NPR];
     int vid[NPR];      // node id of the position (-1: padding)
     uint8_t fls[NPR];
+    int c0s[NPR], c1s[NPR];
+    T rw[NPR];
+    const int d0 = dep_ptr[gt], d1 = dep_ptr[gt + 1];
 #pragma unroll
     for (int q = 0; q < NPR; q++) {
         int sidx = r * NPR + q;
         long long pos = p0 + (UP ? (TN - 1 - sidx) : sidx);
-        uint8_t fl = flags[pos];
-        fls[q] = fl;
-        T val = 0;
-        link[q] = -1;
+        fls[q] = flags[pos];
+        vid[q] = perm[pos];
         link2[q] = -1;
         lcr[q] = -1;
         lce[q] = -1;
-        int v = perm[pos];
-        vid[q] = v;
         if (UP) {
-            if (act && v >= 0) val = yin[(long long)v * k + j];
-            int c0 = lc_ptr[pos], c1 = lc_ptr[pos + 1];
-            if (c1 > c0) link[q] = lc_pos[c0];
-            if (c1 > c0 + 1) link2[q] = lc_pos[c0 + 1];
+            c0s[q] = lc_ptr[pos];
+            c1s[q] = lc_ptr[pos + 1];
+        } else {
+            link[q] = ptop[pos];
+            rw[q] = rpw[pos];
+            T f = F[act ? pos * k + j : 0];
+            vals[q] = act ? f : (T)0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NPR; q++) {
+        if (UP) {
+            const int v = vid[q];
+            const bool okv = act && v >= 0;
+            T y = yin[okv ? (long long)v * k + j : 0];
+            vals[q] = okv ? y : (T)0;
+            const int c0 = c0s[q], c1 = c1s[q];
+            int l0 = lc_pos[c1 > c0 ? c0 : 0];
+            int l1 = lc_pos[c1 > c0 + 1 ? c0 + 1 : 0];
+            link[q] = c1 > c0 ? l0 : -1;
+            link2[q] = c1 > c0 + 1 ? l1 : -1;
             if (c1 > c0 + 2) {
                 lcr[q] = c0 + 2;
                 lce[q] = c1;
             }
         } else {
-            if (act) val = F[pos * k + j] * rpw[pos];
-            if (fl & SEG_TOP) link[q] = ptop[pos];
+            vals[q] = vals[q] * rw[q];
+            if (!(fls[q] & SEG_TOP)) link[q] = -1;
         }
-        vals[q] = val;
     }
+    const int dep_first = dep[d0 + tid < d1 ? d0 + tid : 0];
 
     // cross-level dependencies (tiles of light children / of path parents)
     {
-        int d0 = dep_ptr[gt], d1 = dep_ptr[gt + 1];
         int bad = 0;
         for (int d = d0 + tid; d < d1; d += kThreads) {
-            const unsigned *f = &done[dep[d]];
+            const unsigned *f = &done[d == d0 + tid ? dep_first : dep[d]];
             long long spin = 0;
             while (ld_agent_u32(f) != epoch) {
                 if (++spin > kSpinLimit) {
@@ -308,7 +325,17 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
     }
     __syncthreads();
 
-    // the single dependent hop, then the run-local inclusive segmented scan
+    // the single dependent hop (all of a thread's loads in flight together:
+    // clamped indices, then selects), then the run-local inclusive segmented scan
+    T hop0[NPR], hop1[NPR];
+#pragma unroll
+    for (int q = 0; q < NPR; q++) {
+        const bool ok0 = act && link[q] >= 0, ok1 = UP && act && link2[q] >= 0;
+        T a = ld_agent(UP ? &F[ok0 ? (long long)link[q] * k + j : 0] : &xout[ok0 ? (long long)link[q] * k + j : 0]);
+        T b = UP ? ld_agent(&F[ok1 ? (long long)link2[q] * k + j : 0]) : (T)0;
+        hop0[q] = ok0 ? a : (T)0;
+        hop1[q] = ok1 ? b : (T)0;
+    }
     bool pre[NPR];
     bool seen = false;
     T acc = 0;
@@ -316,13 +343,10 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
     for (int q = 0; q < NPR; q++) {
         T val = vals[q];
         if (act) {
-            if (UP) {
-                if (link[q] >= 0) val += ld_agent(&F[(long long)link[q] * k + j]);
-                if (link2[q] >= 0) val += ld_agent(&F[(long long)link2[q] * k + j]);
+            val += hop0[q];
+            val += hop1[q];
+            if (UP)
                 for (int c = lcr[q]; c >= 0 && c < lce[q]; c++) val += ld_agent(&F[(long long)lc_pos[c] * k + j]);
-            } else {
-                if (link[q] >= 0) val += ld_agent(&xout[(long long)link[q] * k + j]);
-            }
         }
         bool start = UP ? (fls[q] & SEG_BOT) : (fls[q] & SEG_TOP);
         if (start) {
