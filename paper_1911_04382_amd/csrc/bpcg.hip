@@ -75,7 +75,7 @@ struct BlockGram {
         for (int q = 0; q < KP; q++) acc[q] += (A)__shfl(a, q, KP) * bb;
     }
     __device__ void flush(double *s, double *__restrict__ out) {
-        constexpr int G = kThreads / KP;
+        const int G = blockDim.x / KP;
         const int g = threadIdx.x / KP, j = threadIdx.x % KP;
         __syncthreads();
         for (int gg = 0; gg < G; gg++) {
@@ -83,7 +83,7 @@ struct BlockGram {
                 for (int i = 0; i < KP; i++) s[i * KP + j] = (gg ? s[i * KP + j] : 0.0) + (double)acc[i];
             __syncthreads();
         }
-        for (int e = threadIdx.x; e < KP * KP; e += kThreads) st_agent(&out[e], s[e]);
+        for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) st_agent(&out[e], s[e]);
         __syncthreads();
     }
 };
@@ -92,11 +92,12 @@ template <int KP, typename F>
 __device__ __forceinline__ void flush_mfma(double *s, double *__restrict__ out, F &&put) {
     const int w = threadIdx.x >> 6;
     __syncthreads();
-    for (int ww = 0; ww < kThreads / 64; ww++) {
+    const int nw = blockDim.x / 64;
+    for (int ww = 0; ww < nw; ww++) {
         if (w == ww) put(s, ww == 0);
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < KP * KP; e += kThreads) st_agent(&out[e], s[e]);
+    for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) st_agent(&out[e], s[e]);
     __syncthreads();
 }
 template <typename T>
@@ -213,161 +214,140 @@ __device__ bool tail_reduce(double *part, int nblk, int width, int *cnt, double 
 }
 
 // ---------------------------------------------------------- small k x k algebra
-// Right-looking Cholesky A = L L' of the k x k SPD matrix A (row-major, leading
-// dimension KP) in LDS, L in the lower triangle. A pivot below 1e-13 times the
-// largest diagonal entry marks its direction dependent: dead[j] = 1 and column j
-// of L becomes e_j, so the solves below return 0 in that direction.
-template <int KP>
-__device__ void chol_lds(double *A, int k, int *dead) {
-    __shared__ double s_tol;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    if (tid == 0) {
-        double mx = 0.0;
-        for (int i = 0; i < k; i++) mx = fmax(mx, A[i * KP + i]);
-        s_tol = mx * 1e-13;
-    }
-    __syncthreads();
-    for (int jj = 0; jj < k; jj++) {
-        if (tid == 0) {
-            double d = A[jj * KP + jj];
-            bool ok = d > s_tol;
-            dead[jj] = ok ? 0 : 1;
-            A[jj * KP + jj] = ok ? sqrt(d) : 1.0;
-        }
-        __syncthreads();
-        const double piv = A[jj * KP + jj];
-        const bool dj = dead[jj] != 0;
-        for (int i = jj + 1 + tid; i < k; i += nt) {
-            A[i * KP + jj] = dj ? 0.0 : A[i * KP + jj] / piv;
-            A[jj * KP + i] = 0.0;
-        }
-        __syncthreads();
-        const int rem = k - jj - 1;
-        for (int e = tid; e < rem * rem; e += nt) {
-            int i = jj + 1 + e / rem, p = jj + 1 + e % rem;
-            if (p <= i) A[i * KP + p] -= A[i * KP + jj] * A[p * KP + jj];
-        }
-        __syncthreads();
-    }
-}
-// L' X = B in place (back substitution, all columns at once); rows of dead
-// directions are 0
-template <int KP>
-__device__ void chol_back_lds(const double *L, int k, const int *dead, double *B) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = k - 1; i >= 0; i--) {
-        if (tid < k) B[i * KP + tid] = dead[i] ? 0.0 : B[i * KP + tid] / L[i * KP + i];
-        __syncthreads();
-        for (int e = tid; e < i * k; e += nt) {
-            int r = e / k, c = e % k;
-            B[r * KP + c] -= L[i * KP + r] * B[i * KP + c];
-        }
-        __syncthreads();
-    }
-}
-// L L' X = B in place
-template <int KP>
-__device__ void chol_solve_lds(const double *L, int k, const int *dead, double *B) {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int i = 0; i < k; i++) {
-        if (tid < k) B[i * KP + tid] = dead[i] ? 0.0 : B[i * KP + tid] / L[i * KP + i];
-        __syncthreads();
-        const int rem = k - i - 1;
-        for (int e = tid; e < rem * k; e += nt) {
-            int r = i + 1 + e / k, c = e % k;
-            B[r * KP + c] -= L[r * KP + i] * B[i * KP + c];
-        }
-        __syncthreads();
-    }
-    chol_back_lds<KP>(L, k, dead, B);
-}
-// symmetrise the leading k x k block in place; the rest becomes the identity
-template <int KP>
-__device__ void sym_pad(double *A, int k) {
-    for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) {
-        int r = e / KP, c = e % KP;
-        if (r < c) {
-            double a = (r < k && c < k) ? 0.5 * (A[r * KP + c] + A[c * KP + r]) : 0.0;
-            A[r * KP + c] = a;
-            A[c * KP + r] = a;
-        } else if (r == c && r >= k) {
-            A[e] = 1.0;
-        }
-    }
-    __syncthreads();
-}
-
-// Tail operations of the block PCG (the k x k steps, FP64, one workgroup):
-//   ALPHA (tot = [P'Q | P'R]): L = chol(P'Q) kept for BETA; alpha = (P'Q)^-1 P'R
-//   BETA  (tot = Q'Z):         beta = -(P'Q)^-1 Q'Z
-//   NORM  (tot = P'P):         P'P = R'R, rinv = R^-1, zero columns for directions
-//                              P no longer spans (they leave the search block)
-//   STORE (tot = A'B):         the leading k x k block to vec (row-major, ld k)
-enum TailOp : int { TAIL_STORE = 0, TAIL_ALPHA = 1, TAIL_BETA = 2, TAIL_NORM = 3, TAIL_CHECK = 4 };
-// FP64 slots of Vecs::small (KP*KP doubles each)
-enum : int { S_L = 0, S_DEAD = 1 };
+// The k x k steps of the block PCG in FP64 by one workgroup (a separate launch, so
+// that its registers do not lower the occupancy of the streaming kernels):
+//   ALPHA (in = [G | P'R], G = P'Q): Gauss-Jordan on [G | P'R | I] gives
+//          alpha = G^-1 P'R and G^-1 (kept for BETA)
+//   BETA  (in = Q'Z):  beta = -G^-1 Q'Z (a plain product)
+//   NORM  (in = P'P):  forward elimination on [P'P | I] gives P'P = L D L' and
+//          L^-1, so rinv = L^-T D^-1/2 (upper triangular, (P rinv)'(P rinv) = I)
+// G and P'P are symmetric positive semidefinite: they are symmetrised, the
+// elimination needs no pivoting, and a pivot below 1e-13 times the largest
+// diagonal entry marks its direction dependent. That step is skipped and the
+// direction's row of alpha and G^-1 (its column of rinv) is zero: the solves
+// return 0 there and the direction leaves the search block. Only the leading
+// k x k block takes part; everything else is zero.
+enum SmallOp : int { SM_ALPHA = 0, SM_BETA = 1, SM_NORM = 2 };
+enum TailOp : int { TAIL_STORE = 0, TAIL_SAVE = 1, TAIL_CHECK = 2 };
+// FP64 slots of Vecs::small, KP*KP doubles each: G^-1, reduced Gram input (two)
+enum : int { S_GINV = 0, S_IN = 2, S_SLOTS = 4 };
 // working-precision slots of Vecs::smallT (KP*KP each)
 enum : int { T_ALPHA = 0, T_NEGALPHA = 1, T_BETA = 2, T_RINV = 3 };
+
+template <typename T, int KP, int OP>
+__global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ sm, T *__restrict__ outT) {
+    constexpr int KK = KP * KP;
+    constexpr int W = OP == SM_ALPHA ? 3 * KP : 2 * KP;  // [G | RHS | I] or [G | I]
+    constexpr int LD = W + 1;
+    constexpr int NE = (KP * W + kThreads - 1) / kThreads;  // elements per thread
+    __shared__ double M[KP * LD];
+    __shared__ double prow[W];
+    __shared__ double pcol[KP];
+    __shared__ double s_dg;
+    __shared__ int dead[KP];
+    const int tid = threadIdx.x;
+    const double *in = sm + S_IN * KK;
+    double *ginv = sm + S_GINV * KK;
+    if (OP == SM_BETA) {
+        for (int e = tid; e < KK; e += kThreads) {
+            const int r = e / KP, c = e % KP;
+            double acc = 0.0;
+            if (r < k && c < k)
+                for (int p = 0; p < k; p++) acc -= ginv[r * KP + p] * in[p * KP + c];
+            outT[T_BETA * KK + e] = (T)acc;
+        }
+        return;
+    }
+    // this thread's elements of the augmented matrix (fixed for all steps)
+    int er[NE], ec[NE];
+#pragma unroll
+    for (int q = 0; q < NE; q++) {
+        const int e = tid + kThreads * q;
+        er[q] = e < KP * W ? e / W : KP;
+        ec[q] = e % W;
+    }
+#pragma unroll
+    for (int q = 0; q < NE; q++) {
+        const int r = er[q], c = ec[q];
+        if (r >= KP) continue;
+        double x = 0.0;
+        if (r < k) {
+            if (c < KP) x = c < k ? 0.5 * (in[r * KP + c] + in[c * KP + r]) : 0.0;
+            else if (OP == SM_ALPHA && c < 2 * KP) x = c - KP < k ? in[KK + r * KP + (c - KP)] : 0.0;
+            else x = (c - (W - KP)) == r ? 1.0 : 0.0;
+        }
+        M[r * LD + c] = x;
+    }
+    if (tid == 0) {
+        double mx = 0.0;
+        for (int i = 0; i < k; i++) mx = fmax(mx, in[i * KP + i]);
+        s_dg = mx;
+    }
+    __syncthreads();
+    const double tol = s_dg * 1e-13;
+    for (int jj = 0; jj < k; jj++) {
+        const double d = M[jj * LD + jj];
+        const bool ok = d > tol;
+        if (tid == 0) dead[jj] = ok ? 0 : 1;
+        if (ok) {
+            for (int c = tid; c < W; c += kThreads) prow[c] = M[jj * LD + c];
+            if (tid < KP) pcol[tid] = M[tid * LD + jj];
+        }
+        __syncthreads();
+        if (ok) {
+            const double rp = 1.0 / d;
+#pragma unroll
+            for (int q = 0; q < NE; q++) {
+                const int r = er[q], c = ec[q];
+                if (r >= k) continue;
+                if (OP == SM_ALPHA) {
+                    if (r == jj) M[r * LD + c] = prow[c] * rp;
+                    else M[r * LD + c] -= pcol[r] * rp * prow[c];
+                } else if (r > jj) {
+                    M[r * LD + c] -= pcol[r] * rp * prow[c];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (OP == SM_ALPHA) {
+        for (int e = tid; e < KK; e += kThreads) {
+            const int r = e / KP, c = e % KP;
+            const bool live = r < k && c < k && !dead[r];
+            const double a = live ? M[r * LD + KP + c] : 0.0;
+            outT[T_ALPHA * KK + e] = (T)a;
+            outT[T_NEGALPHA * KK + e] = (T)(-a);
+            ginv[e] = live ? M[r * LD + 2 * KP + c] : 0.0;
+        }
+    } else {
+        // rinv[i][j] = (L^-1)[j][i] / sqrt(d_j); row j of L^-1 sits in M[j][KP..2KP)
+        for (int e = tid; e < KK; e += kThreads) {
+            const int i = e / KP, j = e % KP;
+            double x = 0.0;
+            if (i < k && j < k && !dead[j]) x = M[j * LD + KP + i] / sqrt(M[j * LD + j]);
+            outT[T_RINV * KK + e] = (T)x;
+        }
+    }
+}
 
 template <typename T>
 struct Tail {
     double *part;       // level-0 partials (block b at part + b * width), then the level sums
     int *cnt;           // arrival counters, zero between launches
-    double *sm;         // FP64 k x k slots
-    T *outT;            // alpha, -alpha, beta, rinv in working precision
-    double *vec;        // CHECK: squared residual norms; STORE: k x k result
+    double *vec;        // SAVE: the total (width doubles); STORE: k x k result (ld k); CHECK: norms
     const double *rr0;  // CHECK: squared norms of the right-hand sides
     int *count;         // CHECK: number of vectors not yet converged
     double tol2;
     int op;
 };
 
-template <typename T, int KP>
-__device__ void tail_small(const Tail<T> &tl, int k, double *tot) {
-    constexpr int KK = KP * KP;
-    __shared__ int dead[KP];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    int *gdead = reinterpret_cast<int *>(tl.sm + S_DEAD * KK);
-    if (tl.op == TAIL_STORE) {
-        for (int e = tid; e < k * k; e += nt) tl.vec[e] = tot[(e / k) * KP + e % k];
-    } else if (tl.op == TAIL_ALPHA) {
-        double *A = tot, *B = tot + KK;
-        sym_pad<KP>(A, k);
-        chol_lds<KP>(A, k, dead);
-        for (int e = tid; e < KK; e += nt) {
-            tl.sm[S_L * KK + e] = A[e];
-            int r = e / KP, c = e % KP;
-            if (r >= k || c >= k) B[e] = 0.0;
-        }
-        if (tid < KP) gdead[tid] = tid < k ? dead[tid] : 1;
-        __syncthreads();
-        chol_solve_lds<KP>(A, k, dead, B);
-        for (int e = tid; e < KK; e += nt) {
-            tl.outT[T_ALPHA * KK + e] = (T)B[e];
-            tl.outT[T_NEGALPHA * KK + e] = (T)(-B[e]);
-        }
-    } else if (tl.op == TAIL_BETA) {
-        double *B = tot, *L = tot + KK;
-        for (int e = tid; e < KK; e += nt) {
-            L[e] = tl.sm[S_L * KK + e];
-            int r = e / KP, c = e % KP;
-            B[e] = (r < k && c < k) ? -B[e] : 0.0;
-        }
-        if (tid < KP) dead[tid] = gdead[tid];
-        __syncthreads();
-        chol_solve_lds<KP>(L, k, dead, B);
-        for (int e = tid; e < KK; e += nt) tl.outT[T_BETA * KK + e] = (T)B[e];
-    } else if (tl.op == TAIL_NORM) {
-        double *A = tot, *B = tot + KK;
-        sym_pad<KP>(A, k);
-        chol_lds<KP>(A, k, dead);
-        for (int e = tid; e < KK; e += nt) {
-            int r = e / KP, c = e % KP;
-            B[e] = (r == c && r < k) ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        chol_back_lds<KP>(A, k, dead, B);
-        for (int e = tid; e < KK; e += nt) tl.outT[T_RINV * KK + e] = (T)B[e];
+// SAVE / STORE of the reduced total (tot in LDS, width doubles)
+template <int KP>
+__device__ void tail_finish(const double *tot, int width, int k, int op, double *vec) {
+    if (op == TAIL_SAVE) {
+        for (int e = threadIdx.x; e < width; e += blockDim.x) vec[e] = tot[e];
+    } else {
+        for (int e = threadIdx.x; e < k * k; e += blockDim.x) vec[e] = tot[(e / k) * KP + e % k];
     }
 }
 // CHECK: tot = squared residual norms
@@ -386,121 +366,25 @@ __device__ void tail_check(const Tail<T> &tl, int k, const double *tot) {
 }
 
 // ------------------------------------------------------------------ kernels
-// Q = L_P P (grounded at root) and the Gram partials P'Q, P'R of this block; the
-// last block computes alpha.
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_bspmm(long long n, int k, const int *__restrict__ prow,
-                                                    const int *__restrict__ pcol, const T *__restrict__ pval,
-                                                    const T *__restrict__ P, T *__restrict__ Q,
-                                                    const T *__restrict__ R, int root, Tail<T> tl) {
-    constexpr int G = BShape<KP>::G, RPT = BShape<KP>::RPT, CAP = BShape<KP>::CAP;
-    __shared__ int s_ptr[RPT + 1];
-    __shared__ int s_col[CAP];
-    __shared__ T s_val[CAP];
+// Gram partials A'B (and with NG = 2 also A'C) of this block; the last block to
+// finish reduces them.
+template <typename T, int KP, int NG, int NT>
+__global__ __launch_bounds__(NT) void k_bgram(long long n, int k, const T *__restrict__ Am,
+                                              const T *__restrict__ Bm, const T *__restrict__ Cm, Tail<T> tl) {
+    constexpr int G = NT / KP, RPT = G * 4;
     __shared__ double s_w[2 * KP * KP];
     const int tid = threadIdx.x, g = tid / KP, j = tid % KP;
     const bool act = j < k;
-    BlockGram<T, KP> gpq, gpr;
-    gpq.zero();
-    gpr.zero();
-    long long ntile = (n + RPT - 1) / RPT;
-    int t0, t1;
-    tile_range(ntile, t0, t1);
-    for (int tile = t0; tile < t1; tile++) {
-        long long r0 = (long long)tile * RPT;
-        int nrows = (int)min((long long)RPT, n - r0);
-        __syncthreads();
-        for (int i = tid; i <= nrows; i += kThreads) s_ptr[i] = prow[r0 + i];
-        __syncthreads();
-        int base = s_ptr[0], nnz = s_ptr[nrows] - base;
-        bool staged = nnz <= CAP;
-        if (staged)
-            for (int i = tid; i < nnz; i += kThreads) {
-                s_col[i] = pcol[base + i];
-                s_val[i] = pval[base + i];
-            }
-        __syncthreads();
-        // Every lane runs every row step (MFMA needs the whole wave). Loads are
-        // unconditional (clamped index, then a select) so that the rows' own values
-        // and their first two neighbours are all in flight together; further
-        // neighbours (rare in a tree plus a few edges) follow in a loop.
-        constexpr int NIT = RPT / G;
-        T pv[NIT], rv[NIT], x0[NIT], x1[NIT], w0[NIT], w1[NIT];
-        int pp[NIT], pe[NIT];
-#pragma unroll
-        for (int it = 0; it < NIT; it++) {
-            int i = g + it * G;
-            bool ok = act && i < nrows;
-            long long o = ok ? (r0 + i) * k + j : 0;
-            pv[it] = P[o];
-            rv[it] = R[o];
-            pv[it] = ok ? pv[it] : (T)0;
-            rv[it] = ok ? rv[it] : (T)0;
-            int ii = ok ? i : 0;
-            int p0 = s_ptr[ii] - base, p1 = s_ptr[ii + 1] - base;
-            if (!ok) p1 = p0;
-            pp[it] = p0;
-            pe[it] = p1;
-            int c0, c1;
-            if (staged) {
-                c0 = s_col[p0 < p1 ? p0 : 0];
-                c1 = s_col[p0 + 1 < p1 ? p0 + 1 : 0];
-                w0[it] = s_val[p0 < p1 ? p0 : 0];
-                w1[it] = s_val[p0 + 1 < p1 ? p0 + 1 : 0];
-            } else {
-                c0 = pcol[base + (p0 < p1 ? p0 : 0)];
-                c1 = pcol[base + (p0 + 1 < p1 ? p0 + 1 : 0)];
-                w0[it] = pval[base + (p0 < p1 ? p0 : 0)];
-                w1[it] = pval[base + (p0 + 1 < p1 ? p0 + 1 : 0)];
-            }
-            x0[it] = P[p0 < p1 ? (long long)c0 * k + j : 0];
-            x1[it] = P[p0 + 1 < p1 ? (long long)c1 * k + j : 0];
-        }
-#pragma unroll
-        for (int it = 0; it < NIT; it++) {
-            int i = g + it * G;
-            const int p0 = pp[it], p1 = pe[it];
-            T acc = 0;
-            if (p0 < p1) acc += w0[it] * (pv[it] - x0[it]);
-            if (p0 + 1 < p1) acc += w1[it] * (pv[it] - x1[it]);
-            for (int p = p0 + 2; p < p1; p++) {
-                int c = staged ? s_col[p] : pcol[base + p];
-                T w = staged ? s_val[p] : pval[base + p];
-                acc += w * (pv[it] - P[(long long)c * k + j]);
-            }
-            if (act && i < nrows) {
-                long long v = r0 + i;
-                if (v == root) acc = 0;
-                Q[v * k + j] = acc;
-            }
-            gpq.add(pv[it], acc);
-            gpr.add(pv[it], rv[it]);
-        }
-    }
-    constexpr int KK = KP * KP;
-    double *out = tl.part + (long long)blockIdx.x * 2 * KK;
-    gpq.flush(s_w, out);
-    gpr.flush(s_w, out + KK);
-    if (tail_reduce(tl.part, gridDim.x, 2 * KK, tl.cnt, s_w)) tail_small<T, KP>(tl, k, s_w);
-}
-
-// Gram partials A'B of this block; the last block runs the tail operation.
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_bgram(long long n, int k, const T *__restrict__ Am,
-                                                    const T *__restrict__ Bm, Tail<T> tl) {
-    constexpr int G = BShape<KP>::G, RPT = BShape<KP>::RPT;
-    __shared__ double s_w[2 * KP * KP];
-    const int tid = threadIdx.x, g = tid / KP, j = tid % KP;
-    const bool act = j < k;
-    BlockGram<T, KP> g0;
+    BlockGram<T, KP> g0, g1;
     g0.zero();
+    g1.zero();
     long long ntile = (n + RPT - 1) / RPT;
     int t0, t1;
     tile_range(ntile, t0, t1);
     long long v0 = (long long)t0 * RPT, v1 = min(n, (long long)t1 * RPT);
-    constexpr int U = sizeof(T) == 4 ? 8 : 4;  // rows per lane group in flight
+    constexpr int U = (sizeof(T) == 4 ? 8 : 4) / NG;  // rows per lane group in flight
     for (long long vb = v0; vb < v1; vb += (long long)G * U) {  // uniform trip count across the block
-        T av[U], bv[U];
+        T av[U], bv[U], cv[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
             long long v = vb + (long long)u * G + g;
@@ -510,13 +394,22 @@ __global__ __launch_bounds__(kThreads) void k_bgram(long long n, int k, const T 
             bv[u] = Bm[o];
             av[u] = ok ? av[u] : (T)0;
             bv[u] = ok ? bv[u] : (T)0;
+            if (NG == 2) {
+                cv[u] = Cm[o];
+                cv[u] = ok ? cv[u] : (T)0;
+            }
         }
 #pragma unroll
-        for (int u = 0; u < U; u++) g0.add(av[u], bv[u]);
+        for (int u = 0; u < U; u++) {
+            g0.add(av[u], bv[u]);
+            if (NG == 2) g1.add(av[u], cv[u]);
+        }
     }
     constexpr int KK = KP * KP;
-    g0.flush(s_w, tl.part + (long long)blockIdx.x * KK);
-    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_small<T, KP>(tl, k, s_w);
+    double *out = tl.part + (long long)blockIdx.x * NG * KK;
+    g0.flush(s_w, out);
+    if (NG == 2) g1.flush(s_w, out + KK);
+    if (tail_reduce(tl.part, gridDim.x, NG * KK, tl.cnt, s_w)) tail_finish<KP>(s_w, NG * KK, k, tl.op, tl.vec);
 }
 
 // generic R -= Q alpha; per-block squared column norms of R; the last block counts
@@ -601,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_pupdate(long long n, int k, const 
     }
     constexpr int KK = KP * KP;
     gram.flush(s_w, tl.part + (long long)blockIdx.x * KK);
-    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_small<T, KP>(tl, k, s_w);
+    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_finish<KP>(s_w, KK, k, tl.op, tl.vec);
 }
 
 // generic Out = (ADD ? C : 0) + In M (Out may alias In or C)
@@ -771,13 +664,13 @@ __global__ __launch_bounds__(kThreads) void k_mf_rupdate(long long n, int k, con
 // X += P alpha and P_new = Z + P beta from one staged copy of P, the Gram partials
 // of P_new; the last block computes rinv. Persistent: every wave takes the same
 // number of row tiles.
-template <int KP>
-__global__ __launch_bounds__(kThreads) void k_mf_pupdate(long long n, int k, const float *__restrict__ alpha,
-                                                         const float *__restrict__ beta, const float *__restrict__ Z,
-                                                         float *__restrict__ P, float *__restrict__ X,
-                                                         Tail<float> tl) {
+template <int KP, int NT>
+__global__ __launch_bounds__(NT) void k_mf_pupdate(long long n, int k, const float *__restrict__ alpha,
+                                                   const float *__restrict__ beta, const float *__restrict__ Z,
+                                                   float *__restrict__ P, float *__restrict__ X, Tail<float> tl) {
     constexpr int ROWS = MF<KP>::ROWS;
-    __shared__ float sA[4][ROWS * (KP + 1)];
+    constexpr int NW = NT / 64;
+    __shared__ float sA[NW][ROWS * (KP + 1)];
     __shared__ double s_w[2 * KP * KP];
     const int w = threadIdx.x >> 6;
     float bb[MF<KP>::NS], ba[MF<KP>::NS];
@@ -786,9 +679,9 @@ __global__ __launch_bounds__(kThreads) void k_mf_pupdate(long long n, int k, con
     BlockGram<float, KP> gram;
     gram.zero();
     long long ntile = (n + ROWS - 1) / ROWS;
-    long long per = (ntile + (long long)gridDim.x * 4 - 1) / ((long long)gridDim.x * 4);
+    long long per = (ntile + (long long)gridDim.x * NW - 1) / ((long long)gridDim.x * NW);
     int bx = xcd_block(blockIdx.x, gridDim.x);
-    long long t0 = ((long long)bx * 4 + w) * per;
+    long long t0 = ((long long)bx * NW + w) * per;
     for (long long it = 0; it < per; it++) {  // same trip count in every wave
         long long tile = t0 + it;
         long long v0 = tile < ntile ? tile * ROWS : n;  // past the end: zeros, nothing stored
@@ -808,7 +701,7 @@ __global__ __launch_bounds__(kThreads) void k_mf_pupdate(long long n, int k, con
     }
     constexpr int KK = KP * KP;
     gram.flush(s_w, tl.part + (long long)blockIdx.x * KK);
-    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_small<float, KP>(tl, k, s_w);
+    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_finish<KP>(s_w, KK, k, tl.op, tl.vec);
 }
 
 // Out = (ADD ? C : 0) + In M, one row tile per wave (Out may alias In or C: each
@@ -862,20 +755,36 @@ template <typename T, int KP>
 struct UseMF {
     static constexpr bool value = sizeof(T) == 4 && (KP == 16 || KP == 32);
 };
+// Gram launch shape: with MFMA one 1024-thread workgroup per CU (256 partials, two
+// reduction levels), else 256-thread workgroups
+constexpr int kMfGramBlocks = 256;
+template <typename T, int KP, int NG>
+static void launch_gram(const Dims &d, const T *A, const T *B, const T *C, const Tail<T> &tl, hipStream_t s) {
+    if constexpr (UseMF<T, KP>::value)
+        hipLaunchKernelGGL((k_bgram<T, KP, NG, 1024>), dim3(kMfGramBlocks), dim3(1024), 0, s, d.n, d.k, A, B, C, tl);
+    else
+        hipLaunchKernelGGL((k_bgram<T, KP, NG, kThreads>), dim3(gram_blocks(KP)), dim3(kThreads), 0, s, d.n, d.k, A,
+                           B, C, tl);
+}
 template <int KP>
 static int mf_blocks(const Dims &d) {
     return div_up(d.n, 4 * MF<KP>::ROWS);
 }
 
+// tails that save the reduced Gram into the small-matrix input slot
 template <typename T>
-static Tail<T> make_tail(Vecs<T> &v, int op) {
+static Tail<T> save_tail(Vecs<T> &v, const Dims &d) {
     Tail<T> tl{};
     tl.part = v.gpart;
     tl.cnt = v.tcnt;
-    tl.sm = v.small;
-    tl.outT = v.smallT;
-    tl.op = op;
+    tl.vec = v.small + (long long)S_IN * d.kp * d.kp;
+    tl.op = TAIL_SAVE;
     return tl;
+}
+template <typename T, int KP, int OP>
+static void launch_small(const Dims &d, Vecs<T> &v, hipStream_t s) {
+    ProfScope ps(PK_SMALL, 0.0, s);
+    hipLaunchKernelGGL((k_small<T, KP, OP>), dim3(1), dim3(kThreads), 0, s, d.k, v.small, v.smallT);
 }
 
 // R -= Q alpha and the convergence count
@@ -896,9 +805,9 @@ template <typename T, int KP>
 static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s) {
     const int KK = KP * KP;
     ProfScope ps(PK_PUPDATE, 5.0 * d.n * d.k * sizeof(T), s);
-    Tail<T> tl = make_tail(v, TAIL_NORM);
+    Tail<T> tl = save_tail(v, d);
     if constexpr (UseMF<T, KP>::value)
-        hipLaunchKernelGGL((k_mf_pupdate<KP>), dim3(gram_blocks(KP)), dim3(kThreads), 0, s, d.n, d.k,
+        hipLaunchKernelGGL((k_mf_pupdate<KP, 512>), dim3(kMfGramBlocks), dim3(512), 0, s, d.n, d.k,
                            v.smallT + T_ALPHA * KK, v.smallT + T_BETA * KK, v.z, v.p, v.dx, tl);
     else
         hipLaunchKernelGGL((k_pupdate<T, KP>), dim3(gram_blocks(KP)), dim3(kThreads), 0, s, d.n, d.k,
@@ -921,8 +830,8 @@ long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it,
     const long long nk = d.n * d.k;
     const int root = 0;
     const int KK = d.kp * d.kp;
-    const int ngb = gram_blocks(d.kp);
     int *cnt = v.active + kMaxK - 1;
+    const Tail<T> tsave = save_tail(v, d);
     fill_i32(v.tcnt, bpcg_counters(d), 0, s);
     fill_T(v.dx, nk, (T)0, s);
     // P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
@@ -931,13 +840,16 @@ long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it,
     KP_DISPATCH(d.kp, {
         {
             ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
-            hipLaunchKernelGGL((k_bgram<T, KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, v.p, v.p,
-                               make_tail(v, TAIL_NORM));
+            launch_gram<T, KP, 1>(d, v.p, v.p, nullptr, tsave, s);
         }
+        launch_small<T, KP, SM_NORM>(d, v, s);
         launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
     });
     GR_CHECK_LAUNCH();
-    Tail<T> tcheck = make_tail(v, TAIL_CHECK);
+    Tail<T> tcheck{};
+    tcheck.part = v.gpart;
+    tcheck.cnt = v.tcnt;
+    tcheck.op = TAIL_CHECK;
     tcheck.vec = v.red + RED_RR * kMaxK;
     tcheck.rr0 = v.red + RED_RN * kMaxK;
     tcheck.count = cnt;
@@ -947,11 +859,13 @@ long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it,
         it++;
         bool stop = false;
         KP_DISPATCH(d.kp, {
+            // Q = L_P P, then P'Q and P'R in one streaming pass
+            lap_apply<T>(d, t.prow, t.pcol, v.pval, v.p, v.q, root, nullptr, nullptr, s);
             {
-                ProfScope ps(PK_BSPMM, 4.0 * (d.n + 1) + (4.0 + sizeof(T)) * d.p_nnz + 3.0 * nk * sizeof(T), s);
-                hipLaunchKernelGGL((k_bspmm<T, KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol,
-                                   v.pval, v.p, v.q, v.r, root, make_tail(v, TAIL_ALPHA));
+                ProfScope ps(PK_GRAM_PQR, 3.0 * nk * sizeof(T), s);
+                launch_gram<T, KP, 2>(d, v.p, v.q, v.r, tsave, s);
             }
+            launch_small<T, KP, SM_ALPHA>(d, v, s);
             launch_rupdate<T, KP>(d, v, tcheck, s);
             GR_CHECK_LAUNCH();
             if (it >= max_it || (it & 3) == 0) {
@@ -965,10 +879,11 @@ long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it,
                 tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
                 {
                     ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
-                    hipLaunchKernelGGL((k_bgram<T, KP>), dim3(ngb), dim3(kThreads), 0, s, d.n, d.k, v.q, v.z,
-                                       make_tail(v, TAIL_BETA));
+                    launch_gram<T, KP, 1>(d, v.q, v.z, nullptr, tsave, s);
                 }
+                launch_small<T, KP, SM_BETA>(d, v, s);
                 launch_pupdate<T, KP>(d, v, s);
+                launch_small<T, KP, SM_NORM>(d, v, s);
                 launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
             }
             GR_CHECK_LAUNCH();
@@ -990,7 +905,7 @@ void block_gram(const Dims &d, const T *A, const T *B, double *part, int *cnt, d
     tl.vec = out;
     tl.op = TAIL_STORE;
     KP_DISPATCH(d.kp, {
-        hipLaunchKernelGGL((k_bgram<T, KP>), dim3(gram_blocks(d.kp)), dim3(kThreads), 0, s, d.n, d.k, A, B, tl);
+        launch_gram<T, KP, 1>(d, A, B, nullptr, tl, s);
     });
     GR_CHECK_LAUNCH();
 }

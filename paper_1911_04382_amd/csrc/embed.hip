@@ -147,29 +147,51 @@ __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int 
     __syncthreads();
     const T sc = (T)pow2_scale(scale_from);
     double dacc = 0.0;
-    if (j < k) {
-        for (int i = g; i < nrows; i += G) {
-            long long v = r0 + i;
-            T xv = x[v * k + j];
-            T acc = 0;
-            int p = s_ptr[i] - base, pe = s_ptr[i + 1] - base;
-            if (staged) {
-                for (; p + 3 < pe; p += 4) {
-                    T x0 = x[(long long)s_col[p] * k + j], x1 = x[(long long)s_col[p + 1] * k + j];
-                    T x2 = x[(long long)s_col[p + 2] * k + j], x3 = x[(long long)s_col[p + 3] * k + j];
-                    acc += s_val[p] * (xv - x0);
-                    acc += s_val[p + 1] * (xv - x1);
-                    acc += s_val[p + 2] * (xv - x2);
-                    acc += s_val[p + 3] * (xv - x3);
-                }
-                for (; p < pe; p++) acc += s_val[p] * (xv - x[(long long)s_col[p] * k + j]);
-            } else {
-                for (; p < pe; p++) acc += val[base + p] * (xv - x[(long long)col[base + p] * k + j]);
-            }
+    // all rows of this lane group at once: own values and the first four neighbours
+    // are loaded unconditionally (clamped index, then a select); further neighbours
+    // follow in a loop
+    constexpr int NIT = RPB / G;
+    const bool act = j < k;
+    T xv[NIT], xn[NIT][4], wn[NIT][4];
+    int pp[NIT], pe[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int i = g + it * G;
+        const bool ok = act && i < nrows;
+        const T a = x[ok ? (r0 + i) * k + j : 0];
+        xv[it] = ok ? a : (T)0;
+        const int ii = ok ? i : 0;
+        const int p0 = s_ptr[ii] - base, p1 = ok ? s_ptr[ii + 1] - base : p0;
+        pp[it] = p0;
+        pe[it] = p1;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const bool has = p0 + q < p1;
+            const int pq = has ? p0 + q : 0;
+            const int c = staged ? s_col[pq] : col[base + pq];
+            const T w = staged ? s_val[pq] : val[base + pq];
+            const T xc = x[has ? (long long)c * k + j : 0];
+            wn[it][q] = has ? w : (T)0;
+            xn[it][q] = xc;
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; it++) {
+        const int i = g + it * G;
+        T acc = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) acc += wn[it][q] * (xv[it] - xn[it][q]);
+        for (int p = pp[it] + 4; p < pe[it]; p++) {
+            const int c = staged ? s_col[p] : col[base + p];
+            const T w = staged ? s_val[p] : val[base + p];
+            acc += w * (xv[it] - x[(long long)c * k + j]);
+        }
+        if (act && i < nrows) {
+            const long long v = r0 + i;
             acc *= sc;
             if (v == root) acc = 0;
             y[v * k + j] = acc;
-            dacc += (double)xv * (double)acc;
+            dacc += (double)xv[it] * (double)acc;
         }
     }
     if (dot_part) {
@@ -722,7 +744,7 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
                                            (long long)gauss_blocks(d)});
     v.part = a.take<double>(parts * d.kp + 64);
     v.part2 = a.take<double>(64 * d.kp + 64);
-    v.small = a.take<double>(2 * d.kp * d.kp + 64);  // Cholesky factor, dead flags
+    v.small = a.take<double>(4 * d.kp * d.kp + 64);  // Cholesky factor, pivots, Gram input
     v.smallT = a.take<T>(4 * d.kp * d.kp + 64);      // alpha, -alpha, beta, R^-1
     v.gpart = a.take<double>(bpcg_part_doubles(d));
     v.tcnt = a.take<int>(bpcg_counters(d));

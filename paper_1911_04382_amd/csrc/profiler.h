@@ -10,11 +10,12 @@ enum ProfKind : int {
     PK_TREE_UP,     // tree solve, leaf-to-root sweep (k_sweep, up)
     PK_TREE_DOWN,   // tree solve, root-to-leaf sweep (k_sweep, down)
     PK_SCORE,       // edge scoring (k_score)
-    PK_BSPMM,       // block PCG: Q = L_P P with P'Q, P'R and alpha
+    PK_GRAM_PQR,    // block PCG: P'Q and P'R (Q = L_P P is PK_SPMM_P)
     PK_RUPDATE,     // block PCG: R -= Q alpha and the convergence count
-    PK_BGRAM,       // block PCG: Q'Z and beta (also P'P of the first block)
-    PK_PUPDATE,     // block PCG: X += P alpha, P = Z + P beta, P'P and R^-1
+    PK_BGRAM,       // block PCG: Q'Z (also P'P of the first block)
+    PK_PUPDATE,     // block PCG: X += P alpha, P = Z + P beta and P'P
     PK_ROWMUL,      // block PCG: P = P R^-1 (and the last X += P alpha)
+    PK_SMALL,       // block PCG: k x k FP64 steps (alpha, beta, R^-1), one wave
     PK_RESID64,     // FP64 refinement residual (k_resid64)
     PK_START,       // start vectors
     PK_SELECT,      // candidate filter, sort and greedy
