@@ -78,6 +78,59 @@ def cpu_baseline(g, cfg, budget_s=30.0):
     }
 
 
+def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
+    """A plain device-to-device copy of known size (the PMC byte counters of this
+    kernel calibrate FETCH_SIZE / WRITE_SIZE against real bytes)."""
+    import torch
+
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4, "reps": reps}}), flush=True)
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_c2_mesh100_traffic.md")
+SWEEP_SOURCES = ["embed.hip", "embed.h", "common.h", "state.h", "kern.h"]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed PMC summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a device-copy calibration), or None when there is none for
+    this kernel and workload or the kernel's source changed since it was measured."""
+    import hashlib
+
+    if workload != "c2" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1911_04382_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if "=" in line and line.startswith("    "):
+                k, v = (x.strip() for x in line.split("=", 1))
+                vals[k] = v
+    if vals.get("source") != h.hexdigest()[:16]:
+        return None
+    v = vals.get(f"traffic_bytes_per_launch.{kernel}")
+    return float(v) if v is not None else None
+
+
+def percentile(xs, q):
+    ys = sorted(xs)
+    if not ys:
+        return None
+    pos = (len(ys) - 1) * q
+    lo = int(math.floor(pos))
+    hi = min(lo + 1, len(ys) - 1)
+    return ys[lo] + (ys[hi] - ys[lo]) * (pos - lo)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,13 +140,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--opt", action="append", default=[], metavar="KEY=VALUE",
                     help="override a grass_opts field (e.g. pcg_inner_rtol=1e-4)")
-    ap.add_argument("--profile", choices=["all", "none"], default="all",
-                    help="per-kernel event timing during the timed steps")
+    ap.add_argument("--profile", choices=["dominant", "all", "none"], default="dominant",
+                    help="event timing during the timed steps: the dominant kernel only (default), every "
+                         "kernel, or none")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain device copy of known size (PMC calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs a single graph (or batch) per device and has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import torch
 
@@ -109,16 +168,32 @@ def main():
     dg = grass.to_device(g, "cuda:0")
     opts = grass.make_opts(**cfg)
     ws = grass.workspace(dg, opts, "cuda:0")
-    stream = torch.cuda.current_stream()
+
+    # warmup: the first step is timed kernel by kernel (breakdown, dominant kernel)
+    breakdown = None
     for i in range(args.warmup):
+        if i == 0 and args.profile != "none":
+            ctx.profile(True)
         r = grass.grass_sparsify(ctx, dg, opts, ws=ws)
-        log(f"warmup {i}: status {r.status} summary {r.summary}")
-    torch.cuda.synchronize()
-    ctx.profile(args.profile == "all")
+        torch.cuda.synchronize()
+        if i == 0 and args.profile != "none":
+            breakdown = ctx.profile_read()
+            ctx.profile(False)
+        log(f"warmup {i}: status {r.status} passes {r.summary['passes']} pcg iters {r.summary['pcg_iters']}")
+
+    def dominant(prof):
+        cands = [k for k, p in prof.items() if p["launches"] and p["alg_bytes"] > 0]
+        return max(cands, key=lambda k: prof[k]["ms"]) if cands else None
+
+    dom = dominant(breakdown) if breakdown else None
+    if args.profile == "all" or (args.profile == "dominant" and dom is None):
+        ctx.profile(True)
+    elif args.profile == "dominant":
+        ctx.profile(True, kinds=[dom])
     times, summaries, traces = [], [], []
+    torch.cuda.synchronize()
     t_all0 = time.perf_counter()
     for i in range(args.steps):
-        torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = grass.grass_sparsify(ctx, dg, opts, ws=ws)
         torch.cuda.synchronize()
@@ -130,23 +205,32 @@ def main():
             f"added {r.summary['added_edges']}, kappa {r.summary['kappa']:.3f}, pcg iters {r.summary['pcg_iters']}")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all0
-    prof = ctx.profile_read()
+    timed = ctx.profile_read()
     ctx.profile(False)
+    if breakdown is None and args.profile == "all":
+        breakdown = timed
+    if dom is None and args.profile == "all":
+        dom = dominant(timed)
     for tr in traces[-1]:
-        log("  pass", {k: (round(v, 4) if isinstance(v, float) else v) for k, v in tr.items()})
-    for name, p in prof.items():
-        if p["launches"]:
-            gbs = p["alg_bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
-            log(f"  kernel {name:14s} launches {p['launches']:7d} total {p['ms']:9.2f} ms "
-                f"avg {p['ms'] / p['launches'] * 1e3:9.1f} us  alg {gbs:8.1f} GB/s")
+        log("  pass " + ", ".join(f"{k}={v:.6g}" if isinstance(v, float) else f"{k}={v}" for k, v in tr.items()))
+    if breakdown:
+        for name, p in breakdown.items():
+            if p["launches"]:
+                gbs = p["alg_bytes"] / (p["ms"] * 1e-3) / 1e9 if p["ms"] > 0 else 0.0
+                log(f"  kernel {name:14s} launches {p['launches']:7d} total {p['ms']:9.2f} ms "
+                    f"avg {p['ms'] / p['launches'] * 1e3:9.1f} us  alg {gbs:8.1f} GB/s")
     scored = sum(s["scored_edges"] for s in summaries)
     ms_per_step = total / args.steps * 1e3
     value = scored / total
-    # dominant bandwidth-bound kernel family of the timed region
-    cands = [k for k, p in prof.items() if p["launches"] and p["alg_bytes"] > 0]
-    dom = max(cands, key=lambda k: prof[k]["ms"]) if cands else None
-    p = prof[dom] if dom else {"alg_bytes": 0.0, "ms": 1.0, "launches": 1}
-    achieved = p["alg_bytes"] / (p["ms"] * 1e-3) / 1e9
+    roof = None
+    if dom and timed[dom]["launches"]:
+        p = timed[dom]
+        avg_s = p["ms"] * 1e-3 / p["launches"]
+        achieved = p["alg_bytes"] / p["launches"] / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.workload),
+                "traffic_unit": "bytes per launch", "avg_launch_us": avg_s * 1e6,
+                "launches": p["launches"], "alg_bytes_per_launch": p["alg_bytes"] / p["launches"]}
     line = {
         "metric": METRIC,
         "value": value,
@@ -163,12 +247,13 @@ def main():
         "config": {"workload": desc, "n": g.n, "m": g.m, "k": cfg["k"], "t": cfg["t"], "sigma2": cfg["sigma2"],
                    "passes": summaries[-1]["passes"], "added_edges": summaries[-1]["added_edges"],
                    "scored_edges_per_step": summaries[-1]["scored_edges"], "pcg_iters": summaries[-1]["pcg_iters"]},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_us": p["ms"] / p["launches"] * 1e3},
+        "latency_ms": {"p50": percentile(times, 0.5) * 1e3, "p99": percentile(times, 0.99) * 1e3,
+                       "samples": len(times), "path": "plain (one graph per call)"},
+        "roofline": roof,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                        "avg_us": round(v["ms"] / v["launches"] * 1e3, 1),
                         "alg_GBs": round(v["alg_bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
-                    for k, v in prof.items() if v["launches"]},
+                    for k, v in (breakdown or {}).items() if v["launches"]},
     }
     if not args.no_cpu_baseline:
         log("timing the oracle tree pass on the host ...")

@@ -170,19 +170,21 @@ grass_status grass_start_vectors(grass_ctx *ctx, int64_t n, int32_t k, uint64_t 
 grass_status grass_gram(grass_ctx *ctx, int64_t n, int32_t k, int32_t precision, const void *a, const void *b,
                         double *out, void *stream);
 
-/* Diagnostics: per-kernel-family timing with HIP events recorded on the call's
- * stream (adds a few microseconds per timed launch). grass_profile_enable resets
- * the counters; grass_profile_read copies up to cap records (name, launches,
- * summed milliseconds, summed algorithmic bytes: the bytes the operation must
- * move, each vector row read once) and returns the number written (the number
- * available when out is NULL). */
+/* Diagnostics: per-kernel timing with HIP events recorded on the call's stream
+ * around each launch of the selected kernel kinds (a few microseconds per timed
+ * launch). grass_profile_enable(ctx, kinds) resets the counters and times the
+ * kinds whose bit is set (bit i = the i-th record of grass_profile_read; 0 turns
+ * timing off, 0xffffffff times everything). grass_profile_read copies up to cap
+ * records (name, launches, summed milliseconds, summed algorithmic bytes: the
+ * bytes the operation must move, each vector row read once) and returns the
+ * number written (the number available when out is NULL). */
 typedef struct {
     const char *name;
     int64_t launches;
     double total_ms;
     double alg_bytes;
 } grass_kernel_stats;
-grass_status grass_profile_enable(grass_ctx *ctx, int32_t enable);
+grass_status grass_profile_enable(grass_ctx *ctx, uint32_t kinds);
 int32_t grass_profile_read(const grass_ctx *ctx, grass_kernel_stats *out, int32_t cap);
 
 #ifdef __cplusplus

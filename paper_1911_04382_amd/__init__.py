@@ -116,7 +116,7 @@ def load_library(path: str = LIB_PATH):
     L.grass_start_vectors.restype = st
     L.grass_gram.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp]
     L.grass_gram.restype = st
-    L.grass_profile_enable.argtypes = [vp, i32]
+    L.grass_profile_enable.argtypes = [vp, ctypes.c_uint32]
     L.grass_profile_enable.restype = st
     L.grass_profile_read.argtypes = [vp, ctypes.POINTER(grass_kernel_stats), i32]
     L.grass_profile_read.restype = i32
@@ -159,9 +159,18 @@ class Context:
     def last_error(self) -> str:
         return self.lib.grass_last_error(self.h).decode()
 
-    def profile(self, enable: bool = True):
-        """Enable (and reset) per-kernel-family event timing (grass_profile_enable)."""
-        self.check(self.lib.grass_profile_enable(self.h, 1 if enable else 0))
+    def profile(self, enable: bool = True, kinds=None):
+        """Enable (and reset) per-kernel event timing (grass_profile_enable): every
+        kind, or only the named ones (names as returned by profile_read)."""
+        mask = 0
+        if enable:
+            if kinds is None:
+                mask = 0xFFFFFFFF
+            else:
+                names = list(self.profile_read().keys())
+                for k in kinds:
+                    mask |= 1 << names.index(k)
+        self.check(self.lib.grass_profile_enable(self.h, mask))
 
     def profile_read(self) -> dict:
         n = self.lib.grass_profile_read(self.h, None, 0)

@@ -501,9 +501,10 @@ grass_status grass_gram(grass_ctx *ctx, int64_t n, int32_t k, int32_t precision,
     });
 }
 
-grass_status grass_profile_enable(grass_ctx *ctx, int32_t enable) {
+grass_status grass_profile_enable(grass_ctx *ctx, uint32_t kinds) {
     if (!ctx) return GRASS_ERR_INVALID;
-    ctx->prof.on = enable != 0;
+    ctx->prof.on = kinds != 0;
+    ctx->prof.mask = kinds;
     ctx->prof.reset();
     return GRASS_OK;
 }

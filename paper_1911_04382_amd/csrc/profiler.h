@@ -24,6 +24,7 @@ enum ProfKind : int {
 
 struct Profiler {
     bool on = false;
+    uint32_t mask = 0;  // bit i: time kernels of kind i
     struct Rec {
         int kind;
         hipEvent_t a, b;
@@ -81,7 +82,7 @@ struct ProfScope {
     double bytes;
     hipEvent_t a{};
     ProfScope(int kind_, double bytes_, hipStream_t s_) : s(s_), kind(kind_), bytes(bytes_) {
-        if (g_prof && g_prof->on) {
+        if (g_prof && g_prof->on && ((g_prof->mask >> kind_) & 1u)) {
             p = g_prof;
             a = p->get();
             GR_HIP(hipEventRecord(a, s));
