@@ -136,6 +136,57 @@ size_t grass_workspace_bytes(int64_t n, int64_t m, const grass_opts *opts);
 grass_status grass_sparsify(grass_ctx *ctx, const grass_graph *g, const grass_opts *opts, void *workspace,
                             size_t ws_bytes, grass_result *res, void *stream);
 
+/* Many independent graphs in one call (the same method as grass_sparsify, per
+ * graph: Sec. IV-D). graphs, opts, results, statuses: host arrays of count entries
+ * (the grass_graph entries hold device pointers as for grass_sparsify; opts may
+ * hold one entry, used for every graph, when opts_count is 1). Up to `workers`
+ * graphs run at once, each on a HIP stream of its own (ordered after the work
+ * already on `stream`; `stream` waits for all of them) and in its own slice of
+ * the workspace; larger graphs start first. Each graph's outputs are exactly
+ * those grass_sparsify gives it alone. statuses[i] is graph i's status; the call
+ * returns GRASS_OK when every graph converged, GRASS_NOT_CONVERGED when some did
+ * not, or the first error (the other graphs' outputs are still valid when their
+ * status says so). The workspace needs grass_batch_workspace_bytes bytes. */
+size_t grass_batch_workspace_bytes(int32_t count, const grass_graph *graphs, const grass_opts *opts,
+                                   int32_t opts_count, int32_t workers);
+grass_status grass_sparsify_batch(grass_ctx *ctx, int32_t count, const grass_graph *graphs, const grass_opts *opts,
+                                  int32_t opts_count, int32_t workers, void *workspace, size_t ws_bytes,
+                                  grass_result *results, grass_status *statuses, void *stream);
+
+/* Serving: a queue of sparsify requests on one device with continuous batching.
+ * grass_server_create preallocates a device arena of arena_bytes (the admission
+ * budget) and starts `workers` host workers, each with its own HIP stream.
+ * grass_server_submit queues a request and returns at once; a queued request is
+ * admitted as soon as a worker is free and the arena has room for its workspace
+ * (grass_workspace_bytes), in arrival order, smaller requests may pass a head
+ * request that does not fit yet (at most 2 x workers times, then admission waits
+ * for it). Requests in flight overlap on the device. A request's outputs are
+ * exactly those grass_sparsify gives it alone. Its graph and result buffers
+ * (device) and summary/trace (host) must stay valid until it is done or
+ * cancelled. Requests larger than the arena are rejected with GRASS_ERR_OOM at
+ * submission. */
+typedef struct grass_server grass_server;
+typedef enum { GRASS_REQ_QUEUED = 0, GRASS_REQ_RUNNING = 1, GRASS_REQ_DONE = 2, GRASS_REQ_CANCELLED = 3 } grass_req_state;
+typedef struct {
+    int32_t state;        /* grass_req_state */
+    grass_status status;  /* the request's status once done */
+    double t_submit, t_start, t_end; /* seconds since the server was created (steady clock) */
+    size_t footprint;     /* workspace bytes admitted */
+} grass_req_info;
+grass_status grass_server_create(grass_ctx *ctx, size_t arena_bytes, int32_t workers, grass_server **out);
+grass_status grass_server_submit(grass_server *srv, const grass_graph *g, const grass_opts *opts,
+                                 grass_result *res, int64_t *ticket);
+/* State and timing of a request (non-blocking). */
+grass_status grass_server_poll(grass_server *srv, int64_t ticket, grass_req_info *info);
+/* Block until the request is done or cancelled (ticket < 0: until every request is). */
+grass_status grass_server_wait(grass_server *srv, int64_t ticket);
+/* Cancel a request that has not started (GRASS_ERR_INVALID if it has). */
+grass_status grass_server_cancel(grass_server *srv, int64_t ticket);
+/* Text of the last error of a request (empty when none). */
+const char *grass_server_error(grass_server *srv, int64_t ticket);
+/* Wait for the requests in flight, drop the queued ones, free the arena. */
+void grass_server_destroy(grass_server *srv);
+
 /* Maximum-weight spanning tree (Boruvka; ties by smaller edge id): tree_mask[e] = 1
  * for the n-1 tree edges, else 0. tree_mask: device uint8 [m]. */
 grass_status grass_spanning_tree(grass_ctx *ctx, const grass_graph *g, uint8_t *tree_mask, void *workspace,

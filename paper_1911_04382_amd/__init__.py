@@ -72,6 +72,17 @@ class grass_kernel_stats(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double)]
 
 
+class grass_req_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("footprint", ctypes.c_size_t)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED = 0, 1, 2, 3
+
+
 class grass_result(ctypes.Structure):
     _fields_ = [("edge_mask", ctypes.c_void_p), ("scores", ctypes.c_void_p),
                 ("summary", ctypes.POINTER(grass_summary)), ("trace", ctypes.POINTER(grass_pass_stats)),
@@ -120,6 +131,26 @@ def load_library(path: str = LIB_PATH):
     L.grass_profile_enable.restype = st
     L.grass_profile_read.argtypes = [vp, ctypes.POINTER(grass_kernel_stats), i32]
     L.grass_profile_read.restype = i32
+    L.grass_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(grass_graph), ctypes.POINTER(grass_opts), i32, i32]
+    L.grass_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.grass_sparsify_batch.argtypes = [vp, i32, ctypes.POINTER(grass_graph), ctypes.POINTER(grass_opts), i32, i32,
+                                       vp, ctypes.c_size_t, ctypes.POINTER(grass_result), ctypes.POINTER(st), vp]
+    L.grass_sparsify_batch.restype = st
+    L.grass_server_create.argtypes = [vp, ctypes.c_size_t, i32, ctypes.POINTER(vp)]
+    L.grass_server_create.restype = st
+    L.grass_server_submit.argtypes = [vp, ctypes.POINTER(grass_graph), ctypes.POINTER(grass_opts),
+                                      ctypes.POINTER(grass_result), ctypes.POINTER(i64)]
+    L.grass_server_submit.restype = st
+    L.grass_server_poll.argtypes = [vp, i64, ctypes.POINTER(grass_req_info)]
+    L.grass_server_poll.restype = st
+    L.grass_server_wait.argtypes = [vp, i64]
+    L.grass_server_wait.restype = st
+    L.grass_server_cancel.argtypes = [vp, i64]
+    L.grass_server_cancel.restype = st
+    L.grass_server_error.argtypes = [vp, i64]
+    L.grass_server_error.restype = ctypes.c_char_p
+    L.grass_server_destroy.argtypes = [vp]
+    L.grass_server_destroy.restype = None
     _lib = L
     return L
 
@@ -271,6 +302,109 @@ def grass_sparsify(ctx: Context, g: DeviceGraph, opts: grass_opts, ws=None, stre
                                           _stream_ptr(stream)))
     trace = [tr[i].as_dict() for i in range(min(summ.passes, trace_cap))]
     return SparsifyResult(rc, mask, scores, summ.as_dict(), trace)
+
+
+def _result_buffers(g: DeviceGraph, opts: grass_opts, trace_cap: int):
+    torch = _torch()
+    dev = g.src.device
+    mask = torch.empty(g.m, dtype=torch.uint8, device=dev)
+    scores = torch.empty(g.m, dtype=torch.float64 if opts.precision == 64 else torch.float32, device=dev)
+    summ = grass_summary()
+    tr = (grass_pass_stats * trace_cap)()
+    res = grass_result(mask.data_ptr(), scores.data_ptr(), ctypes.pointer(summ),
+                       ctypes.cast(tr, ctypes.POINTER(grass_pass_stats)), trace_cap)
+    return mask, scores, summ, tr, res
+
+
+def batch_workspace(graphs, opts, workers: int, device="cuda:0"):
+    """A uint8 device tensor of grass_batch_workspace_bytes()."""
+    torch = _torch()
+    opts_list = opts if isinstance(opts, (list, tuple)) else [opts]
+    gcs = (grass_graph * len(graphs))(*[g.c() for g in graphs])
+    oc = (grass_opts * len(opts_list))(*opts_list)
+    nbytes = load_library().grass_batch_workspace_bytes(len(graphs), gcs, oc, len(opts_list), workers)
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def grass_sparsify_batch(ctx: Context, graphs, opts, workers: int = 8, ws=None, stream=None, trace_cap=256):
+    """grass_sparsify_batch: (status, one SparsifyResult per graph). opts: one
+    grass_opts for every graph, or a list with one per graph. A graph that fails
+    carries its own status; the call raises only when no graph ran."""
+    opts_list = opts if isinstance(opts, (list, tuple)) else [opts]
+    n = len(graphs)
+    bufs = [_result_buffers(g, opts_list[0 if len(opts_list) == 1 else i], trace_cap) for i, g in enumerate(graphs)]
+    gcs = (grass_graph * n)(*[g.c() for g in graphs])
+    oc = (grass_opts * len(opts_list))(*opts_list)
+    rs = (grass_result * n)(*[b[4] for b in bufs])
+    sts = (ctypes.c_int * n)()
+    if ws is None:
+        ws = batch_workspace(graphs, opts, workers, graphs[0].src.device)
+    rc = ctx.lib.grass_sparsify_batch(ctx.h, n, gcs, oc, len(opts_list), workers, ctypes.c_void_p(ws.data_ptr()),
+                                      int(ws.numel()), rs, sts, _stream_ptr(stream))
+    if rc < 0 and all(sts[i] >= 0 for i in range(n)):  # the call itself failed (no graph ran)
+        ctx.check(rc)
+    out = []
+    for i, (mask, scores, summ, tr, _) in enumerate(bufs):
+        trace = [tr[j].as_dict() for j in range(min(summ.passes, trace_cap))]
+        out.append(SparsifyResult(sts[i], mask, scores, summ.as_dict(), trace))
+    return rc, out
+
+
+class Server:
+    """grass_server_*: a serving queue with admission by HBM footprint."""
+
+    def __init__(self, ctx: Context, arena_bytes: int, workers: int = 4):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        h = ctypes.c_void_p()
+        ctx.check(self.lib.grass_server_create(ctx.h, int(arena_bytes), workers, ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, g: DeviceGraph, opts: grass_opts, trace_cap=64) -> int:
+        mask, scores, summ, tr, res = _result_buffers(g, opts, trace_cap)
+        gc = g.c()
+        oc = grass_opts.from_buffer_copy(opts)
+        t = ctypes.c_int64()
+        self.ctx.check(self.lib.grass_server_submit(self.h, ctypes.byref(gc), ctypes.byref(oc), ctypes.byref(res),
+                                                    ctypes.byref(t)))
+        # everything the request points to stays alive until it is collected
+        self._keep[t.value] = (g, mask, scores, summ, tr, res, gc, oc, trace_cap)
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        info = grass_req_info()
+        self.ctx.check(self.lib.grass_server_poll(self.h, ticket, ctypes.byref(info)))
+        return info.as_dict()
+
+    def wait(self, ticket: int = -1):
+        self.ctx.check(self.lib.grass_server_wait(self.h, ticket))
+
+    def cancel(self, ticket: int):
+        return self.lib.grass_server_cancel(self.h, ticket)
+
+    def error(self, ticket: int) -> str:
+        return self.lib.grass_server_error(self.h, ticket).decode()
+
+    def result(self, ticket: int) -> SparsifyResult:
+        """The outputs of a finished request (waits for it)."""
+        self.wait(ticket)
+        info = self.poll(ticket)
+        g, mask, scores, summ, tr, res, gc, oc, cap = self._keep[ticket]
+        trace = [tr[j].as_dict() for j in range(min(summ.passes, cap))]
+        return SparsifyResult(info["status"], mask, scores, summ.as_dict(), trace)
+
+    def close(self):
+        if self.h:
+            self.lib.grass_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def grass_spanning_tree(ctx: Context, g: DeviceGraph, ws=None, stream=None):

@@ -5,19 +5,12 @@
 #include <cmath>
 #include <mutex>
 
+#include "driver.h"
 #include "embed.h"
 #include "graph.h"
 #include "kern.h"
 #include "profiler.h"
 #include "select.h"
-
-struct grass_ctx {
-    int device = 0;
-    std::string last_error;
-    void *own_ws = nullptr;
-    size_t own_bytes = 0;
-    grass::Profiler prof;
-};
 
 namespace grass {
 thread_local Profiler *g_prof = nullptr;
@@ -334,6 +327,17 @@ void check_graph(const grass_graph *g) {
 }
 
 }  // namespace
+
+void check_graph_args(const grass_graph *g) { check_graph(g); }
+void check_opts_args(const grass_opts &o) { check_opts(o); }
+size_t sparsify_bytes(const grass_graph &g, const grass_opts &o) { return plan_bytes(g.n, g.m, o.k, o.precision); }
+grass_status sparsify_run(grass_ctx *ctx, const grass_graph &g, const grass_opts &o, void *ws, size_t ws_bytes,
+                          grass_result *res, hipStream_t s) {
+    require(ws != nullptr, GRASS_ERR_INVALID, "a workspace is required");
+    if (o.precision == 64) return sparsify_impl<double>(ctx, g, o, ws, ws_bytes, res, s);
+    return sparsify_impl<float>(ctx, g, o, ws, ws_bytes, res, s);
+}
+
 }  // namespace grass
 
 using namespace grass;

@@ -1,0 +1,153 @@
+"""Batched and served sparsification (C ABI grass_sparsify_batch, grass_server_*):
+every graph's outputs must be exactly those grass_sparsify gives it alone (same
+kernels, deterministic reductions, so bit for bit), whatever else runs beside it;
+admission, cancellation and error statuses behave as the header states. One
+batched FP64 result is also checked against the oracle directly."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1911_04382_amd import graphs as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a ROCm GPU", allow_module_level=True)
+
+import paper_1911_04382_amd as grass  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = grass.Context(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def mixed_graphs():
+    return [
+        G.grid2d(40, 30, seed=1),
+        G.mesh3d(10, 9, 8, weights=(G.W_LOGUNIFORM10, -3, 3), seed=2),
+        G.ba(3000, seed=3),
+        G.rgg(2500, seed=4),
+        G.grid2d(64, 64, seed=5),
+        G.mesh3d(14, 14, 14, seed=6),
+        G.ba(1200, seed=7),
+        G.grid2d_longrange(45, seed=8),
+    ]
+
+
+def same(a, b):
+    assert a.status == b.status
+    assert torch.equal(a.mask, b.mask)
+    assert torch.equal(a.scores, b.scores)
+    for key in ("lambda_max", "lambda_min", "passes", "added_edges", "pcg_iters"):
+        assert a.summary[key] == b.summary[key], key
+
+
+@pytest.fixture(scope="module")
+def alone(ctx):
+    gs = mixed_graphs()
+    dgs = [grass.to_device(g, DEV) for g in gs]
+    opts = grass.make_opts(k=8, t=2, precision=32, seed=3, sigma2=60.0, max_iters=12)
+    res = [grass.grass_sparsify(ctx, dg, opts) for dg in dgs]
+    torch.cuda.synchronize()
+    return gs, dgs, opts, res
+
+
+@pytest.mark.parametrize("workers", [1, 3, 8])
+def test_batch_equals_alone(ctx, alone, workers):
+    gs, dgs, opts, ref = alone
+    say("batch of", len(dgs), "graphs, workers", workers)
+    rc, out = grass.grass_sparsify_batch(ctx, dgs, opts, workers=workers)
+    assert rc in (grass.OK, grass.NOT_CONVERGED)
+    for a, b in zip(out, ref):
+        same(a, b)
+
+
+def test_batch_per_graph_opts_and_error_status(ctx):
+    g1 = G.grid2d(20, 20, seed=1)
+    g = G.grid2d(8, 8)
+    keep = (g.src != 0) & (g.dst != 0)
+    disc = G.Graph(g.n, g.src[keep], g.dst[keep], g.w[keep])
+    dgs = [grass.to_device(x, DEV) for x in (g1, disc, g1)]
+    o1 = grass.make_opts(k=4, t=2, seed=1, sigma2=50.0)
+    o2 = grass.make_opts(k=4, t=2, seed=1, sigma2=50.0)
+    o3 = grass.make_opts(k=8, t=3, seed=2, sigma2=30.0)
+    say("batch with a disconnected graph and per-graph opts")
+    rc, out = grass.grass_sparsify_batch(ctx, dgs, [o1, o2, o3], workers=2)
+    assert rc == grass.ERR_DISCONNECTED
+    assert out[1].status == grass.ERR_DISCONNECTED
+    same(out[0], grass.grass_sparsify(ctx, dgs[0], o1))
+    same(out[2], grass.grass_sparsify(ctx, dgs[2], o3))
+
+
+def test_batch_fp64_matches_oracle(ctx):
+    gs = [G.config_c1(), G.grid2d(30, 20, seed=9)]
+    dgs = [grass.to_device(g, DEV) for g in gs]
+    opts = grass.make_opts(k=8, t=2, precision=64, seed=0, max_iters=1, sigma2=100.0)
+    say("batch FP64 vs oracle")
+    rc, out = grass.grass_sparsify_batch(ctx, dgs, opts, workers=2)
+    for g, r in zip(gs, out):
+        ref = O.sparsify(g, sigma2=100.0, k=8, t=2, seed=0, max_iters=1)
+        assert np.array_equal(r.mask.cpu().numpy(), ref.mask)
+        np.testing.assert_allclose(r.scores.cpu().numpy(), ref.scores, atol=1e-10)
+
+
+def test_server_alone_and_in_the_mix(ctx, alone):
+    gs, dgs, opts, ref = alone
+    need = [grass.load_library().grass_workspace_bytes(dg.n, dg.m, opts) for dg in dgs]
+    arena = int(sum(sorted(need)[-2:]) * 1.1)  # room for about two requests at once
+    say("server: arena", arena, "bytes, footprints", need)
+    srv = grass.Server(ctx, arena, workers=4)
+    try:
+        tickets = [srv.submit(dg, opts) for dg in dgs]
+        srv.wait()
+        infos = [srv.poll(t) for t in tickets]
+        for t, b, info in zip(tickets, ref, infos):
+            assert info["state"] == grass.REQ_DONE, srv.error(t)
+            same(srv.result(t), b)
+            assert info["t_submit"] <= info["t_start"] <= info["t_end"]
+        # the arena held at most what fits: no two admitted requests overlapped beyond it
+        events = sorted([(i["t_start"], i["footprint"]) for i in infos] + [(i["t_end"], -i["footprint"]) for i in infos])
+        used = peak = 0
+        for _, d in events:
+            used += d
+            peak = max(peak, used)
+        assert peak <= arena
+        # a request larger than the arena is refused at submission
+        with pytest.raises(grass.GrassError):
+            srv.submit(grass.to_device(G.mesh3d(40, 40, 40), DEV), opts)
+    finally:
+        srv.close()
+
+
+def test_server_cancel_and_requeue(ctx, alone):
+    gs, dgs, opts, ref = alone
+    srv = grass.Server(ctx, 1 << 30, workers=1)
+    try:
+        say("server: cancel a queued request")
+        t0 = srv.submit(dgs[5], opts)
+        t1 = srv.submit(dgs[0], opts)
+        t2 = srv.submit(dgs[1], opts)
+        cancelled = srv.cancel(t2) == grass.OK
+        srv.wait()
+        assert srv.poll(t0)["state"] == grass.REQ_DONE
+        assert srv.poll(t1)["state"] == grass.REQ_DONE
+        if cancelled:
+            assert srv.poll(t2)["state"] == grass.REQ_CANCELLED
+            assert srv.poll(t2)["status"] == grass.ERR_CANCELLED
+        else:  # it had already started
+            assert srv.poll(t2)["state"] == grass.REQ_DONE
+        assert srv.cancel(t0) != grass.OK  # finished requests cannot be cancelled
+        same(srv.result(t0), ref[5])
+        same(srv.result(t1), ref[0])
+    finally:
+        srv.close()
