@@ -131,6 +131,107 @@ def percentile(xs, q):
     return ys[lo] + (ys[hi] - ys[lo]) * (pos - lo)
 
 
+def run_batch(args, grass, torch):
+    """C4: many independent graphs. The plain path sparsifies them one after another
+    on one stream; grass_sparsify_batch runs `workers` at once."""
+    from paper_1911_04382_amd import graphs as G
+
+    sizes = G.config_c4_sizes(256)[: args.count]
+    gs = [G.config_c4_graph(kind, n, seed=i) for i, (kind, n) in enumerate(sizes)]
+    dgs = [grass.to_device(g, "cuda:0") for g in gs]
+    opts = grass.make_opts(k=16, t=2, sigma2=100.0, precision=32)
+    ctx = grass.Context(0)
+    torch.cuda.synchronize()
+    log(f"C4: {len(gs)} graphs, {sum(g.n for g in gs)} nodes, {sum(g.m for g in gs)} edges")
+    t0 = time.perf_counter()
+    plain = [grass.grass_sparsify(ctx, dg, opts) for dg in dgs]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    ws = grass.batch_workspace(dgs, opts, args.workers)
+    t0 = time.perf_counter()
+    rc, out = grass.grass_sparsify_batch(ctx, dgs, opts, workers=args.workers, ws=ws)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(torch.equal(a.mask, b.mask) and torch.equal(a.scores, b.scores) for a, b in zip(out, plain))
+    scored = sum(r.summary["scored_edges"] for r in out)
+    line = {"metric": "off-tree edges scored/sec, batch of independent graphs", "value": scored / t_batch,
+            "unit": "edges/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"C4: first {len(gs)} of 256 graphs cycling 2D mesh / 3D mesh / RGG, n log-uniform "
+                                   "[1e3, 2e5], U[1,10), k=16, t=2, sigma^2=100",
+                       "graphs": len(gs), "nodes": sum(g.n for g in gs), "workers": args.workers,
+                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
+            "batch_s": t_batch, "plain_s": t_plain, "plain_value": scored / t_plain, "speedup": t_plain / t_batch,
+            "identical_to_plain": same,
+            "statuses": {str(k): sum(1 for r in out if r.status == k) for k in sorted({r.status for r in out})}}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def run_serving(args, grass, torch):
+    """C5: a Poisson stream of sparsify requests on preferential-attachment graphs.
+    Plain path: one request at a time in arrival order on one stream. Server:
+    continuous batching with admission by workspace footprint. Both see the same
+    arrival times; latency = completion - arrival."""
+    import numpy as np
+    from paper_1911_04382_amd import graphs as G
+
+    sizes = G.config_c5_sizes(args.count, lo=1e4, hi=args.c5_max_n, seed=1)
+    gs = [G.config_c5_graph(int(n), seed=100 + i) for i, n in enumerate(sizes)]
+    dgs = [grass.to_device(g, "cuda:0") for g in gs]
+    opts = grass.make_opts(k=16, t=2, sigma2=100.0, precision=32)
+    ctx = grass.Context(0)
+    torch.cuda.synchronize()
+    # plain-path service times (also the capacity that sets the arrival rate)
+    ws = grass.workspace(max(dgs, key=lambda d: d.n + d.m), opts, "cuda:0")
+    service = []
+    for dg in dgs:
+        t0 = time.perf_counter()
+        grass.grass_sparsify(ctx, dg, opts, ws=ws)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+    mu = 1.0 / (sum(service) / len(service))
+    rate = args.rho * mu
+    rng = np.random.Generator(np.random.Philox(key=1))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(dgs)))
+    log(f"C5: {len(dgs)} requests, n in [{min(g.n for g in gs)}, {max(g.n for g in gs)}], mean service "
+        f"{1e3 / mu:.0f} ms, arrival rate {rate:.2f}/s (rho {args.rho})")
+    # plain FIFO at these arrival times (simulated clock: service times measured above)
+    clock, lat_plain = 0.0, []
+    for a, sv in zip(arrivals, service):
+        clock = max(clock, a) + sv
+        lat_plain.append(clock - a)
+    # the server, live
+    need = max(grass.load_library().grass_workspace_bytes(d.n, d.m, opts) for d in dgs)
+    srv = grass.Server(ctx, max(need * args.workers, int(args.arena_gb * (1 << 30))), workers=args.workers)
+    t0 = time.perf_counter()
+    tickets = []
+    for a, dg in zip(arrivals, dgs):
+        dt = t0 + a - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(dg, opts))
+    srv.wait()
+    infos = [srv.poll(t) for t in tickets]
+    lat_srv = [i["t_end"] - i["t_submit"] for i in infos]
+    ok = all(i["state"] == grass.REQ_DONE and i["status"] >= 0 for i in infos)
+    scored = sum(srv.result(t).summary["scored_edges"] for t in tickets)
+    makespan = max(i["t_end"] for i in infos) - min(i["t_submit"] for i in infos)
+    srv.close()
+    line = {"metric": "sparsify latency p50/p99 under a Poisson request stream (server vs plain path)",
+            "value": percentile(lat_srv, 0.99) * 1e3, "unit": "ms (p99, server)", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"C5: {len(dgs)} Barabasi-Albert requests (m=5), n from p(n)~n^-2 on "
+                                   f"[1e4, {args.c5_max_n:.0e}], U[0.1,1), k=16, t=2, sigma^2=100, Poisson arrivals at "
+                                   f"rho={args.rho} of plain capacity",
+                       "workers": args.workers, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
+            "server_ms": {"p50": percentile(lat_srv, 0.5) * 1e3, "p99": percentile(lat_srv, 0.99) * 1e3},
+            "plain_ms": {"p50": percentile(lat_plain, 0.5) * 1e3, "p99": percentile(lat_plain, 0.99) * 1e3},
+            "server_edges_per_s": scored / makespan, "all_done": ok,
+            "mean_service_ms": 1e3 / mu, "arrival_rate_per_s": rate}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +246,11 @@ def main():
                          "kernel, or none")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (PMC calibration)")
+    ap.add_argument("--count", type=int, default=64, help="c4: graphs; c5: requests")
+    ap.add_argument("--workers", type=int, default=8, help="c4/c5: concurrent graphs")
+    ap.add_argument("--rho", type=float, default=0.7, help="c5: arrival rate / plain-path capacity")
+    ap.add_argument("--c5-max-n", type=float, default=1e5, help="c5: largest request (nodes)")
+    ap.add_argument("--arena-gb", type=float, default=16.0, help="c5: server arena (GiB)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs a single graph (or batch) per device and has no "
@@ -153,10 +259,18 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.workload in ("c4", "c5"):
+        # concurrent graphs need hardware queues beyond HIP's default of 4
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(16, max(4, args.workers))))
 
     import torch
 
     import paper_1911_04382_amd as grass
+
+    if args.workload == "c4":
+        return run_batch(args, grass, torch)
+    if args.workload == "c5":
+        return run_serving(args, grass, torch)
 
     g, cfg, desc = workload(args.workload)
     for kv in args.opt:

@@ -826,38 +826,44 @@ static void launch_rowmul(const Dims &d, const T *M, const T *In, const T *C, T 
 }
 
 template <typename T>
-long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it, hipStream_t s) {
+SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s) {
     const long long nk = d.n * d.k;
     const int root = 0;
     const int KK = d.kp * d.kp;
     int *cnt = v.active + kMaxK - 1;
     const Tail<T> tsave = save_tail(v, d);
+    SolveInfo info;
     fill_i32(v.tcnt, bpcg_counters(d), 0, s);
-    fill_T(v.dx, nk, (T)0, s);
-    // P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
-    tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
-    hipLaunchKernelGGL(k_copy_vec<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.z, v.p);
-    KP_DISPATCH(d.kp, {
-        {
-            ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
-            launch_gram<T, KP, 1>(d, v.p, v.p, nullptr, tsave, s);
-        }
-        launch_small<T, KP, SM_NORM>(d, v, s);
-        launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
-    });
-    GR_CHECK_LAUNCH();
+    // r = b - L_P x with x = 0; its norms are the reference of the first inner phase
+    info.resid64 = true_residual<T>(t, v, d, b, false, s);
+    if (info.resid64 <= pp.rtol) return info;
+    // a fresh search block: P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
+    auto start_block = [&]() {
+        tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
+        hipLaunchKernelGGL(k_copy_vec<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.z, v.p);
+        KP_DISPATCH(d.kp, {
+            {
+                ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
+                launch_gram<T, KP, 1>(d, v.p, v.p, nullptr, tsave, s);
+            }
+            launch_small<T, KP, SM_NORM>(d, v, s);
+            launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
+        });
+        GR_CHECK_LAUNCH();
+    };
+    start_block();
     Tail<T> tcheck{};
     tcheck.part = v.gpart;
     tcheck.cnt = v.tcnt;
     tcheck.op = TAIL_CHECK;
     tcheck.vec = v.red + RED_RR * kMaxK;
-    tcheck.rr0 = v.red + RED_RN * kMaxK;
+    tcheck.rr0 = v.red + RED_RN * kMaxK;  // squared norms at the last replacement
     tcheck.count = cnt;
-    tcheck.tol2 = itol * itol;
+    tcheck.tol2 = pp.itol * pp.itol;
     long long it = 0;
     while (true) {
         it++;
-        bool stop = false;
+        bool stop = false, restart = false;
         KP_DISPATCH(d.kp, {
             // Q = L_P P, then P'Q and P'R in one streaming pass
             lap_apply<T>(d, t.prow, t.pcol, v.pval, v.p, v.q, root, nullptr, nullptr, s);
@@ -868,14 +874,19 @@ long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it,
             launch_small<T, KP, SM_ALPHA>(d, v, s);
             launch_rupdate<T, KP>(d, v, tcheck, s);
             GR_CHECK_LAUNCH();
-            if (it >= max_it || (it & 3) == 0) {
-                if (it >= max_it || read_i32(cnt, s) == 0) {
-                    // the last step's X += P alpha
+            const bool last = it >= pp.max_it;
+            if (last || (it & 3) == 0) {
+                if (last || read_i32(cnt, s) == 0) {
+                    // every vector's recursive residual fell by itol since the last
+                    // refinement step: X += P alpha, fold X into the FP64 solution,
+                    // recompute the residual there and restart from it
                     launch_rowmul<T, KP, true>(d, v.smallT + T_ALPHA * KK, v.p, v.dx, v.dx, s);
-                    stop = true;
+                    info.resid64 = true_residual<T>(t, v, d, b, true, s);
+                    if (last || info.resid64 <= pp.rtol || info.outer >= pp.max_repl) stop = true;
+                    else restart = true;
                 }
             }
-            if (!stop) {
+            if (!stop && !restart) {
                 tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
                 {
                     ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
@@ -889,8 +900,13 @@ long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it,
             GR_CHECK_LAUNCH();
         });
         if (stop) break;
+        if (restart) {
+            info.outer++;
+            start_block();
+        }
     }
-    return it;
+    info.iters = it;
+    return info;
 }
 
 // Diagnostics: C = A'B (FP64, k x k, row-major ld k) for device n x k blocks,
@@ -913,7 +929,9 @@ template void block_gram<float>(const Dims &, const float *, const float *, doub
 template void block_gram<double>(const Dims &, const double *, const double *, double *, int *, double *,
                                  hipStream_t);
 
-template long long block_pcg<float>(Topo &, Vecs<float> &, const Dims &, double, int, hipStream_t);
-template long long block_pcg<double>(Topo &, Vecs<double> &, const Dims &, double, int, hipStream_t);
+template SolveInfo block_pcg<float>(Topo &, Vecs<float> &, const Dims &, const float *, const PcgParams &,
+                                    hipStream_t);
+template SolveInfo block_pcg<double>(Topo &, Vecs<double> &, const Dims &, const double *, const PcgParams &,
+                                     hipStream_t);
 
 }  // namespace grass

@@ -34,9 +34,13 @@ template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s);
 
-// L_P solve by FP32 (or FP64) PCG with the tree preconditioner, refined in FP64
-// until ||b - L_P x||_2 <= rtol ||b||_2 per vector. Returns inner iterations
-// (max over vectors, summed over refinement steps) and the FP64 relative residual.
+// L_P solve: block PCG in working precision with the tree preconditioner, refined
+// in FP64: whenever every vector's recursive residual has fallen by
+// pcg_inner_rtol, the correction moves into the FP64 solution, the residual is
+// recomputed in FP64 and the block PCG restarts from it. (Keeping the search block
+// across the replacement instead diverged on ill-conditioned meshes in FP32.)
+// Ends when ||b - L_P x||_2 <= pcg_rtol ||b||_2 per vector (FP64). Returns the
+// iterations, the FP64 relative residual and the number of restarts.
 struct SolveInfo {
     long long iters = 0;
     double resid64 = 0.0;
@@ -44,6 +48,11 @@ struct SolveInfo {
 };
 template <typename T>
 SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s);
+
+// x64 += dx, dx = 0 when fold; r = b - L_P x64 in FP64 (stored in v.r), squared
+// norms in red[RED_RN]; returns max_j ||r_j|| / ||b_j|| (b norms in red[RED_BN]).
+template <typename T>
+double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, bool fold, hipStream_t s);
 
 // Score every edge: heat (optional output), FP64 per-vector sums over E and over P,
 // max heat over the edges not in P. Then reduce to lambda_max (host reads).
@@ -60,12 +69,14 @@ template <typename T>
 void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride, int offset, double *out,
              hipStream_t s);
 
-// Inner block PCG (block size k, tree preconditioner): on entry r holds the
-// right-hand side (grounded row zeroed) and red[RED_RN] its squared column norms;
-// on exit dx approximates L_P^+ r to a relative residual itol per vector, r holds
-// the residual. Returns the iteration count.
+// Block PCG (block size k, tree preconditioner) with FP64 refinement restarts;
+// x64 and dx hold zero and red[RED_BN] the squared norms of b on entry.
+struct PcgParams {
+    double rtol = 1e-6, itol = 1e-3;
+    int max_it = 2000, max_repl = 6;
+};
 template <typename T>
-long long block_pcg(Topo &t, Vecs<T> &v, const Dims &d, double itol, int max_it, hipStream_t s);
+SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s);
 
 // Scratch of the block PCG's in-kernel reductions: doubles of Vecs::gpart and
 // counters of Vecs::tcnt.

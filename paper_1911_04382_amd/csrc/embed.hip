@@ -653,10 +653,14 @@ __global__ __launch_bounds__(kThreads) void k_norm2(long long n, int k, const T 
     }
 }
 
+// x64 += dx; dx = 0 (the correction accumulated in working precision moves into
+// the FP64 solution)
 template <typename T>
-__global__ void k_add_dx(long long nk, double *__restrict__ x64, const T *__restrict__ dx) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (long long)gridDim.x * blockDim.x)
+__global__ void k_fold_dx(long long nk, double *__restrict__ x64, T *__restrict__ dx) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (long long)gridDim.x * blockDim.x) {
         x64[i] += (double)dx[i];
+        dx[i] = (T)0;
+    }
 }
 
 template <typename T>
@@ -835,14 +839,41 @@ void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride
 }
 
 template <typename T>
+double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, bool fold, hipStream_t s) {
+    const long long nk = d.n * d.k;
+    const int nbv = vec_blocks(d);
+    if (fold) {
+        hipLaunchKernelGGL(k_fold_dx<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, v.dx);
+        GR_CHECK_LAUNCH();
+    }
+    {
+        ProfScope ps(PK_RESID64, 4.0 * (d.n + 1) + 12.0 * d.p_nnz + (double)d.n * d.k * (8 + 2 * sizeof(T)), s);
+        KP_DISPATCH(d.kp, {
+            hipLaunchKernelGGL((k_resid64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol,
+                               t.pval64, b, v.x64, v.r, 0, v.part, nbv);
+        });
+    }
+    GR_CHECK_LAUNCH();
+    double *bn = v.red + RED_BN * kMaxK, *rn = v.red + RED_RN * kMaxK;
+    col_sum<T>(d, v, v.part, nbv, d.kp, 0, rn, s);
+    std::vector<double> hb(2 * kMaxK);
+    GR_HIP(hipMemcpyAsync(hb.data(), bn, 2 * kMaxK * sizeof(double), hipMemcpyDeviceToHost, s));
+    GR_HIP(hipStreamSynchronize(s));
+    double worst = 0.0;
+    for (int j = 0; j < d.k; j++) {
+        double bj = std::sqrt(hb[j]), rj = std::sqrt(hb[kMaxK + j]);
+        double rel = bj > 0 ? rj / bj : 0.0;
+        worst = rel > worst ? rel : worst;
+    }
+    return worst;
+}
+
+template <typename T>
 SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s) {
-    SolveInfo info;
     const long long nk = d.n * d.k;
     const int root = 0;
-    const int nbl = lap_blocks(d);
     const int nbv = vec_blocks(d);
-    double *red = v.red;
-    double *bn = red + RED_BN * kMaxK, *rn = red + RED_RN * kMaxK;
+    double *bn = v.red + RED_BN * kMaxK;
     // ||b|| per vector (grounded rows)
     KP_DISPATCH(d.kp, {
         hipLaunchKernelGGL((k_norm2<T, KP>), dim3(nbv), dim3(kThreads), 0, s, d.n, d.k, b, root, v.part);
@@ -850,39 +881,13 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     GR_CHECK_LAUNCH();
     col_sum<T>(d, v, v.part, nbv, d.kp, 0, bn, s);
     fill_f64(v.x64, nk, 0.0, s);
-    std::vector<double> hb(2 * kMaxK);
-    const double rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
-    const double itol = o.pcg_inner_rtol > 0 ? o.pcg_inner_rtol : 1e-3;
-    const int max_outer = o.pcg_max_outer > 0 ? o.pcg_max_outer : 6;
-    const int max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
-    for (int outer = 0;; outer++) {
-        {
-            ProfScope ps(PK_RESID64,
-                         4.0 * (d.n + 1) + 12.0 * d.p_nnz + (double)d.n * d.k * (8 + 2 * sizeof(T)), s);
-            KP_DISPATCH(d.kp, {
-                hipLaunchKernelGGL((k_resid64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow,
-                                   t.pcol, t.pval64, b, v.x64, v.r, root, v.part, nbv);
-            });
-        }
-        GR_CHECK_LAUNCH();
-        col_sum<T>(d, v, v.part, nbv, d.kp, 0, rn, s);
-        GR_HIP(hipMemcpyAsync(hb.data(), bn, 2 * kMaxK * sizeof(double), hipMemcpyDeviceToHost, s));
-        GR_HIP(hipStreamSynchronize(s));
-        double worst = 0.0;
-        for (int j = 0; j < d.k; j++) {
-            double bj = std::sqrt(hb[j]), rj = std::sqrt(hb[kMaxK + j]);
-            double rel = bj > 0 ? rj / bj : 0.0;
-            worst = rel > worst ? rel : worst;
-        }
-        info.resid64 = worst;
-        info.outer = outer;
-        if (worst <= rtol || outer >= max_outer) break;
-        // inner block PCG on the residual: dx ~ L_P^+ r
-        long long it = block_pcg<T>(t, v, d, itol, max_it, s);
-        info.iters += it;
-        hipLaunchKernelGGL(k_add_dx<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, v.dx);
-        GR_CHECK_LAUNCH();
-    }
+    fill_T(v.dx, nk, (T)0, s);
+    PcgParams pp;
+    pp.rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
+    pp.itol = o.pcg_inner_rtol > 0 ? o.pcg_inner_rtol : 1e-3;
+    pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
+    pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 6;
+    SolveInfo info = block_pcg<T>(t, v, d, b, pp, s);
     fill_u32(reinterpret_cast<unsigned *>(v.u64s + U_ABSMAX), 2, 0u, s);
     hipLaunchKernelGGL(k_x64_out<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, x, v.u64s + U_ABSMAX);
     GR_CHECK_LAUNCH();
@@ -933,6 +938,7 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
                                const unsigned long long *, double *, hipStream_t);                               \
     template void tree_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const T *, double *,            \
                                 unsigned long long *, hipStream_t);                                              \
+    template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, bool, hipStream_t);            \
     template SolveInfo pcg_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const grass_opts &,         \
                                     hipStream_t);                                                                \
     template void score_edges<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, hipStream_t);                  \
