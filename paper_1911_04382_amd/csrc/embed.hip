@@ -207,6 +207,41 @@ __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int 
 }
 
 // ------------------------------------------------------------ tree solve
+// Tagged words: a 32-bit payload and a 32-bit tag in one 64-bit agent-scope atomic,
+// so a reader that sees the tag it waits for also holds the data (no separate
+// flag, no store-completion wait on the writer). A double takes two words.
+template <typename T>
+__device__ __forceinline__ void tag_put(unsigned long long *p, T v, unsigned tag) {
+    const unsigned long long t = (unsigned long long)tag << 32;
+    if constexpr (sizeof(T) == 4) {
+        st_agent_u64(p, t | __float_as_uint(v));
+    } else {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        st_agent_u64(p, t | (b & 0xffffffffull));
+        st_agent_u64(p + 1, t | (b >> 32));
+    }
+}
+// bounded spin until every word of the value carries `epoch` (tag >> 1); false on
+// time-out
+template <typename T>
+__device__ __forceinline__ bool tag_get(const unsigned long long *p, unsigned epoch, T &v, unsigned &tag) {
+    long long spin = 0;
+    while (true) {
+        const unsigned long long w0 = ld_agent_u64(p);
+        const unsigned long long w1 = sizeof(T) == 8 ? ld_agent_u64(p + 1) : w0;
+        if ((unsigned)(w0 >> 33) == (epoch & 0x7fffffffu) && (unsigned)(w1 >> 33) == (epoch & 0x7fffffffu)) {
+            tag = (unsigned)(w0 >> 32);
+            if constexpr (sizeof(T) == 4)
+                v = __uint_as_float((unsigned)w0);
+            else
+                v = __longlong_as_double((long long)((w1 << 32) | (w0 & 0xffffffffull)));
+            return true;
+        }
+        if (++spin > kSpinLimit) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
 // One sweep of the grounded tree solve over the heavy-light layout, all levels in
 // one launch. Paths are contiguous segments of the layout (top to bottom):
 //   UP   (reverse scan, segments start at path bottoms):
@@ -216,18 +251,20 @@ __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int 
 // Tiles take an atomic ticket in processing order (UP: deepest level first,
 // tiles in reverse; DOWN: root level first). A tile first waits for the tiles
 // it depends on in other levels (precomputed lists: the tiles of its light
-// children, or of its paths' parents), then scans, publishes its aggregate,
+// children, or of its paths' parents), then scans, publishes its aggregate as
+// tagged words (tag: sweep epoch and whether the tile holds a segment start),
 // looks back within its level to the nearest tile holding a segment start (adding
 // aggregates in a fixed order, so results never depend on timing), writes its
 // outputs and stamps itself done. Every awaited tile holds a smaller ticket, so
 // it is already running; every wait is bounded. Data another tile reads inside
 // the same launch moves through agent-scope (XCD-coherent) loads and stores.
 template <typename T, int KP, bool UP>
-__global__ __launch_bounds__(kThreads) void k_sweep(
-    int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm, const uint8_t *__restrict__ flags,
+__device__ __forceinline__ void sweep_tile(
+    int tk, int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm,
+    const uint8_t *__restrict__ flags,
     const int *__restrict__ ptop, const int *__restrict__ lc_ptr, const int *__restrict__ lc_pos,
     const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F, T *__restrict__ xout,
-    T *__restrict__ agg, int *__restrict__ hs, unsigned *__restrict__ status, unsigned *__restrict__ done,
+    unsigned long long *__restrict__ aggw, unsigned *__restrict__ done,
     const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
     int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
     double *__restrict__ dot_part, unsigned long long *__restrict__ absmax) {
@@ -248,7 +285,6 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
     const int j = tid % KP, r = tid / KP;
     const unsigned epoch = epoch_ptr[0] + (UP ? 0u : 1u);
     if (tid == 0) {
-        int tk = atomicAdd(ticket, 1);
         int acc = 0;
         s_info[0] = 0;
         s_info[1] = 1;
@@ -394,35 +430,39 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
             else carry += s_agg[rr][j];
             any |= s_hs[rr];
         }
-        st_agent(&agg[gt * KP + j], carry);
-        if (j == 0) st_agent_i32(&hs[gt], any);
-        wait_mem();
-        if (j == 0) st_agent_u32(&status[gt], epoch);
+        const unsigned tag = (epoch << 1) | (unsigned)any;
+        constexpr int TW = sizeof(T) / 4;
+        tag_put<T>(&aggw[(gt * KP + j) * TW], carry, tag);
         uint8_t f0 = flags[p0 + (UP ? (TN - 1) : 0)];
         bool first_start = UP ? (f0 & SEG_BOT) : (f0 & SEG_TOP);
         T cin = 0;
         if (!first_start) {
+            // nearest predecessor holding a segment start: each step is one tagged
+            // load that gives readiness, the start bit and the value together
             int cnt = 0;
             int bad = 1;  // cleared when a tile holding a segment start is reached
+            T first = 0;
             const int npred = UP ? (ntiles - 1 - lt) : lt;  // tiles before this one in scan order
             for (int back = 1; back <= npred; back++) {
                 long long pg = (long long)lvl_first + (UP ? (lt + back) : (lt - back));
-                long long spin = 0;
-                while (ld_agent_u32(&status[pg]) != epoch) {
-                    if (++spin > kSpinLimit) break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                if (spin > kSpinLimit) break;
+                T val;
+                unsigned tg;
+                if (!tag_get<T>(&aggw[(pg * KP + j) * TW], epoch, val, tg)) break;
                 cnt = back;
-                if (ld_agent_i32(&hs[pg])) {
+                first = val;
+                if (tg & 1u) {
                     bad = 0;
                     break;
                 }
             }
             if (bad && j == 0) atomicOr(devflags, DEVERR_SPIN);
-            for (int back = cnt; back >= 1; back--) {
+            // fixed order: from the segment-start tile towards this one
+            cin = first;
+            for (int back = cnt - 1; back >= 1; back--) {
                 long long pg = (long long)lvl_first + (UP ? (lt + back) : (lt - back));
-                cin += ld_agent(&agg[pg * KP + j]);
+                T val;
+                unsigned tg;
+                if (tag_get<T>(&aggw[(pg * KP + j) * TW], epoch, val, tg)) cin += val;
             }
         }
         s_carry[j] = cin;
@@ -445,7 +485,8 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
         } else {
             int v = vid[q];
             if (v >= 0 && act) {
-                st_agent(&xout[(long long)v * k + j], out);  // may be read as a path parent's potential
+                if (fls[q] & SEG_LC) st_agent(&xout[(long long)v * k + j], out);  // a path parent's potential
+                else xout[(long long)v * k + j] = out;
                 if (rdot) dacc += (double)rdot[(long long)v * k + j] * (double)out;
                 double ao = fabs((double)out);
                 mx = ao > mx ? ao : mx;
@@ -480,6 +521,35 @@ __global__ __launch_bounds__(kThreads) void k_sweep(
                 if (m2 > 0.0) atomicMax(absmax, (unsigned long long)__double_as_longlong(m2));
             }
         }
+    }
+}
+
+// Tiles per ticket: a workgroup takes a chunk of consecutive tickets with one atomic
+// and processes its tiles in order (the tile of ticket t only waits for tiles of
+// smaller tickets, which earlier chunks or this workgroup already hold, so the
+// holder of the smallest unfinished ticket always progresses). One atomic per
+// tile serialised the launch on the counter.
+constexpr int kTilesPerTicket = 1;
+
+template <typename T, int KP, bool UP>
+__global__ __launch_bounds__(kThreads) void k_sweep(
+    int ntiles_total, int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm,
+    const uint8_t *__restrict__ flags, const int *__restrict__ ptop, const int *__restrict__ lc_ptr,
+    const int *__restrict__ lc_pos, const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F,
+    T *__restrict__ xout, unsigned long long *__restrict__ aggw, unsigned *__restrict__ done,
+    const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
+    int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
+    double *__restrict__ dot_part, unsigned long long *__restrict__ absmax) {
+    __shared__ int s_base;
+    if (threadIdx.x == 0) s_base = atomicAdd(ticket, kTilesPerTicket);
+    __syncthreads();
+    const int base = s_base;
+    for (int c = 0; c < kTilesPerTicket; c++) {
+        const int tk = base + c;
+        if (tk >= ntiles_total) break;
+        sweep_tile<T, KP, UP>(tk, nlev, lvl_tile, k, perm, flags, ptop, lc_ptr, lc_pos, rpw, yin, F, xout, aggw, done,
+                              epoch_ptr, dep_ptr, dep, ticket, devflags, rdot, dot_part, absmax);
+        __syncthreads();
     }
 }
 
@@ -735,7 +805,7 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
     v.H = a.take<T>(nk);
     v.Y = a.take<T>(nk);
     v.F = a.take<T>((d.Npad + 1) * d.k);
-    v.agg = a.take<T>(d.ntiles * d.kp);
+    v.aggw = a.take<unsigned long long>(d.ntiles * d.kp * (long long)(sizeof(T) / 4));
     v.heat = a.take<T>(m);
     v.r = a.take<T>(nk);
     v.z = a.take<T>(nk);
@@ -791,23 +861,22 @@ template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s) {
     const int nt = (int)t.ntiles_used;
+    const int nblk = (nt + kTilesPerTicket - 1) / kTilesPerTicket;
     const double vbytes = 2.0 * d.n * d.k * sizeof(T);
     hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(64), 0, s, t.tickets, t.epoch_dev);
     KP_DISPATCH(d.kp, {
         {
             // y in, subtree sums out; per node: flags, perm, light-child pointers
             ProfScope ps(PK_TREE_UP, vbytes + 13.0 * d.n, s);
-            hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nt), dim3(kThreads), 0, s, t.nlev, t.lvl_tile, d.k,
-                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status,
-                               t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
+            hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nblk), dim3(kThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
+                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
                                (double *)nullptr, (unsigned long long *)nullptr);
         }
         {
             // subtree sums in, potentials out; per node: flags, perm, path top, 1/w
             ProfScope ps(PK_TREE_DOWN, vbytes + (9.0 + sizeof(T)) * d.n, s);
-            hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nt), dim3(kThreads), 0, s, t.nlev, t.lvl_tile, d.k,
-                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.agg, t.hs, t.status,
-                               t.done, t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part,
+            hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nblk), dim3(kThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
+                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part,
                                absmax);
         }
     });

@@ -389,7 +389,7 @@ __global__ void k_layout_pad(long long N, int *__restrict__ perm, uint8_t *__res
 }
 __global__ void k_lc_count(long long n, const int *__restrict__ tptr, const int *__restrict__ tcol,
                            const int *__restrict__ parent, const int *__restrict__ heavy, const int *__restrict__ lp,
-                           int *__restrict__ lcc) {
+                           int *__restrict__ lcc, uint8_t *__restrict__ flags) {
     GSTRIDE(u, n) {
         int c = 0;
         for (int a = tptr[u]; a < tptr[u + 1]; a++) {
@@ -397,6 +397,7 @@ __global__ void k_lc_count(long long n, const int *__restrict__ tptr, const int 
             if (parent[v] == u && v != heavy[u]) c++;
         }
         lcc[lp[u]] = c;
+        if (c > 0) flags[lp[u]] |= SEG_LC;
     }
 }
 __global__ void k_lc_fill(long long n, const int *__restrict__ tptr, const int *__restrict__ tcol,
@@ -527,9 +528,7 @@ void plan_topo(Arena &a, const Dims &d, Topo &t, SetupTmp &st) {
     t.ptop = a.take<int>(d.Npad + 1);
     t.lc_ptr = a.take<int>(d.Npad + 1);
     t.lc_pos = a.take<int>(n);
-    t.status = a.take<unsigned>(d.ntiles);
     t.done = a.take<unsigned>(d.ntiles);
-    t.hs = a.take<int>(d.ntiles);
     t.tickets = a.take<int>(2 * kMaxLevels);
     t.epoch_dev = a.take<unsigned>(4);
     t.lvl_tile = a.take<int>(kMaxLevels + 1);
@@ -752,7 +751,7 @@ void build_tree(Topo &t, Vecs<T> &v, const Dims &d, SetupTmp &st, hipStream_t s)
     hipLaunchKernelGGL(k_layout<T>, dim3(grid_for(n)), dim3(256), 0, s, n, t.head, t.off, pbase, t.heavy, t.parent,
                        t.pw, t.lp, t.perm, t.flags, t.ptop, v.rpw);
     hipLaunchKernelGGL(k_lc_count, dim3(grid_for(n)), dim3(256), 0, s, n, tptr, tcol, t.parent, t.heavy, t.lp,
-                       t.lc_ptr);
+                       t.lc_ptr, t.flags);
     GR_CHECK_LAUNCH();
     scan_excl_i32(t.lc_ptr, t.lc_ptr, t.N + 1, nullptr, t.scan, s);
     hipLaunchKernelGGL(k_lc_fill, dim3(grid_for(n)), dim3(256), 0, s, n, tptr, tcol, t.parent, t.heavy, t.lp, t.lc_ptr,
@@ -798,8 +797,8 @@ void build_tree(Topo &t, Vecs<T> &v, const Dims &d, SetupTmp &st, hipStream_t s)
             scan_excl_i32(cntv, ptr, NT + 1, nullptr, t.scan, s);
         }
     }
-    fill_u32(t.status, d.ntiles, 0u, s);
     fill_u32(t.done, d.ntiles, 0u, s);
+    fill_u32(reinterpret_cast<unsigned *>(v.aggw), 2 * d.ntiles * d.kp * (long long)(sizeof(T) / 4), 0u, s);
     fill_u32(t.epoch_dev, 4, 0u, s);
     t.epoch = 0;
     GR_HIP(hipStreamSynchronize(s));

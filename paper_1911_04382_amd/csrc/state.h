@@ -8,10 +8,10 @@ namespace grass {
 
 constexpr int kMaxLevels = 64;   // light depth <= log2(n) < 32; margin
 constexpr int kSolveThreads = 256;
-constexpr int kSolveNPR = 8;     // nodes per run in the tree-solve scans
+constexpr int kSolveNPR = 16;    // nodes per run in the tree-solve scans
 constexpr int kMaxK = 64;
 
-enum : uint8_t { SEG_TOP = 1, SEG_BOT = 2 };
+enum : uint8_t { SEG_TOP = 1, SEG_BOT = 2, SEG_LC = 4 };  // path top, path bottom, has light children
 
 // Sizes that fix the workspace plan.
 struct Dims {
@@ -63,9 +63,7 @@ struct Topo {
     int *lc_ptr = nullptr;         // [Npad+1]
     int *lc_pos = nullptr;         // [n]
     // tile scan state
-    unsigned *status = nullptr;    // [ntiles] aggregate published (epoch stamp)
     unsigned *done = nullptr;      // [ntiles] outputs written (epoch stamp)
-    int *hs = nullptr;             // [ntiles]
     int *tickets = nullptr;        // [2*kMaxLevels]: sweep tickets
     unsigned *epoch_dev = nullptr; // [2]: current sweep epoch (device-side, advanced per solve)
     int *lvl_tile = nullptr;       // [kMaxLevels+1] first tile of each level (layout order), device
@@ -91,7 +89,7 @@ struct Vecs {
     T *rpw = nullptr;     // [Npad] 1/parent weight in layout order
     T *H = nullptr, *Y = nullptr;  // [n*kp]
     T *F = nullptr;       // [Npad*kp] subtree currents (layout order)
-    T *agg = nullptr;     // [ntiles*kp]
+    unsigned long long *aggw = nullptr;  // [ntiles*kp*sizeof(T)/4] tagged tile aggregates of the sweeps
     T *heat = nullptr;    // [m] (internal heat when the caller gives none)
     // PCG
     T *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dx = nullptr;  // [n*kp]
