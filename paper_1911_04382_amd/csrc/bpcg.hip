@@ -243,17 +243,28 @@ __global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ 
     __shared__ double M[KP * LD];
     __shared__ double prow[W];
     __shared__ double pcol[KP];
+    // the reduced Gram input (and G^-1 for BETA), staged with coalesced loads
+    // before any dependent work (read in place for the widest blocks, LDS-bound)
+    constexpr bool STAGE = KP <= 32;
+    __shared__ double s_in[STAGE ? 2 * KK : 1];
     __shared__ double s_dg;
     __shared__ int dead[KP];
     const int tid = threadIdx.x;
     const double *in = sm + S_IN * KK;
     double *ginv = sm + S_GINV * KK;
+    if (STAGE) {
+        for (int e = tid; e < (OP == SM_NORM ? KK : 2 * KK); e += kThreads)
+            s_in[e] = OP == SM_BETA ? (e < KK ? in[e] : ginv[e - KK]) : in[e];
+        __syncthreads();
+    }
+    const double *src = STAGE ? s_in : in;
     if (OP == SM_BETA) {
+        const double *qz = src, *gi = STAGE ? s_in + KK : ginv;
         for (int e = tid; e < KK; e += kThreads) {
             const int r = e / KP, c = e % KP;
             double acc = 0.0;
             if (r < k && c < k)
-                for (int p = 0; p < k; p++) acc -= ginv[r * KP + p] * in[p * KP + c];
+                for (int p = 0; p < k; p++) acc -= gi[r * KP + p] * qz[p * KP + c];
             outT[T_BETA * KK + e] = (T)acc;
         }
         return;
@@ -272,16 +283,17 @@ __global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ 
         if (r >= KP) continue;
         double x = 0.0;
         if (r < k) {
-            if (c < KP) x = c < k ? 0.5 * (in[r * KP + c] + in[c * KP + r]) : 0.0;
-            else if (OP == SM_ALPHA && c < 2 * KP) x = c - KP < k ? in[KK + r * KP + (c - KP)] : 0.0;
+            if (c < KP) x = c < k ? 0.5 * (src[r * KP + c] + src[c * KP + r]) : 0.0;
+            else if (OP == SM_ALPHA && c < 2 * KP) x = c - KP < k ? src[KK + r * KP + (c - KP)] : 0.0;
             else x = (c - (W - KP)) == r ? 1.0 : 0.0;
         }
         M[r * LD + c] = x;
     }
-    if (tid == 0) {
+    if (tid < 64) {  // largest diagonal entry, one wave
         double mx = 0.0;
-        for (int i = 0; i < k; i++) mx = fmax(mx, in[i * KP + i]);
-        s_dg = mx;
+        for (int i = tid; i < k; i += 64) mx = fmax(mx, src[i * KP + i]);
+        for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+        if (tid == 0) s_dg = mx;
     }
     __syncthreads();
     const double tol = s_dg * 1e-13;
@@ -382,7 +394,7 @@ __global__ __launch_bounds__(NT) void k_bgram(long long n, int k, const T *__res
     int t0, t1;
     tile_range(ntile, t0, t1);
     long long v0 = (long long)t0 * RPT, v1 = min(n, (long long)t1 * RPT);
-    constexpr int U = (sizeof(T) == 4 ? 8 : 4) / NG;  // rows per lane group in flight
+    constexpr int U = sizeof(T) == 4 ? 8 : 4;  // rows per lane group in flight
     for (long long vb = v0; vb < v1; vb += (long long)G * U) {  // uniform trip count across the block
         T av[U], bv[U], cv[U];
 #pragma unroll
