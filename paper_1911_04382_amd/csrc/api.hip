@@ -128,7 +128,7 @@ PassResult run_pass(Session<T> &S, const grass_opts &o, int pass, bool use_pcg, 
     unsigned long long *absmax = v.u64s + U_ABSMAX;
     int steps = o.lambda_steps > o.t ? o.lambda_steps : o.t;
     for (int step = 1; step <= steps; step++) {
-        lap_apply<T>(d, t.rowptr, t.col, v.cval, H, Y, -1, step > 1 ? absmax : nullptr, nullptr, s);
+        lap_apply<T>(d, t.rowptr, t.col, v.cval, v.eg, H, Y, -1, step > 1 ? absmax : nullptr, nullptr, s);
         fill_u32(reinterpret_cast<unsigned *>(absmax), 2, 0u, s);
         if (!use_pcg) {
             tree_solve<T>(t, v, d, Y, Y, nullptr, nullptr, absmax, s);

@@ -878,7 +878,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
         bool stop = false, restart = false;
         KP_DISPATCH(d.kp, {
             // Q = L_P P, then P'Q and P'R in one streaming pass
-            lap_apply<T>(d, t.prow, t.pcol, v.pval, v.p, v.q, root, nullptr, nullptr, s);
+            lap_apply<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, v.q, root, nullptr, nullptr, s);
             {
                 ProfScope ps(PK_GRAM_PQR, 3.0 * nk * sizeof(T), s);
                 launch_gram<T, KP, 2>(d, v.p, v.q, v.r, tsave, s);

@@ -106,88 +106,67 @@ __device__ __forceinline__ double pow2_scale(const unsigned long long *slot) {
     return ldexp(1.0, -ilogb(mx));
 }
 
-// y = L x for the rows of one block: the block's CSR slice (row pointers,
-// neighbour ids, weights) is staged in LDS with coalesced loads, so every row then
-// costs only the gathers of its neighbours' vector rows (k contiguous values).
-// Difference form: y_v = sum_u w_vu (x_v - x_u) keeps FP32 accurate for smooth x.
-template <int KP>
+// y = L x for k vectors at once over the padded first E entries of each row (rows
+// longer than E finish from the CSR). The difference form y_v = sum_u w_vu (x_v -
+// x_u) keeps FP32 accurate for smooth x.
+// A lane group of KP lanes owns one row per step; all NIT rows of a group issue
+// their loads together: own values and the neighbour lists first, then the
+// neighbour rows, so a block costs two dependent memory rounds and no barrier.
+template <int E>
 struct LapShape {
-    static constexpr int G = kThreads / KP;            // lane groups per block
-    static constexpr int RPB = G * 4;                  // rows per block
-    static constexpr int CAP = RPB * 12 < 3072 ? RPB * 12 : 3072;  // staged nonzeros (fast path)
+    static constexpr int NIT = E <= 4 ? 4 : 2;  // rows per lane group
 };
 
-template <typename T, int KP>
+template <typename T, int KP, int E>
 __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int *__restrict__ rowptr,
                                                   const int *__restrict__ col, const T *__restrict__ val,
-                                                  const T *__restrict__ x, T *__restrict__ y, int root,
+                                                  const int *__restrict__ ecol, const T *__restrict__ eval,
+                                                  const int *__restrict__ edeg, const T *__restrict__ x,
+                                                  T *__restrict__ y, int root,
                                                   const unsigned long long *__restrict__ scale_from,
                                                   double *__restrict__ dot_part, int nblk) {
-    constexpr int G = LapShape<KP>::G;
-    constexpr int RPB = LapShape<KP>::RPB;
-    constexpr int CAP = LapShape<KP>::CAP;
-    __shared__ int s_ptr[RPB + 1];
-    __shared__ int s_col[CAP];
-    __shared__ T s_val[CAP];
+    constexpr int G = kThreads / KP;
+    constexpr int NIT = LapShape<E>::NIT;
+    constexpr int RPB = G * NIT;
     int b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= nblk) return;
     const int tid = threadIdx.x;
     const int g = tid / KP, j = tid % KP;
-    const long long r0 = (long long)b * RPB;
-    const int nrows = (int)min((long long)RPB, n - r0);
-    for (int i = tid; i <= nrows; i += kThreads) s_ptr[i] = rowptr[r0 + i];
-    __syncthreads();
-    const int base = s_ptr[0], nnz = s_ptr[nrows] - base;
-    const bool staged = nnz <= CAP;
-    if (staged)
-        for (int i = tid; i < nnz; i += kThreads) {
-            s_col[i] = col[base + i];
-            s_val[i] = val[base + i];
-        }
-    __syncthreads();
-    const T sc = (T)pow2_scale(scale_from);
-    double dacc = 0.0;
-    // all rows of this lane group at once: own values and the first four neighbours
-    // are loaded unconditionally (clamped index, then a select); further neighbours
-    // follow in a loop
-    constexpr int NIT = RPB / G;
     const bool act = j < k;
-    T xv[NIT], xn[NIT][4], wn[NIT][4];
-    int pp[NIT], pe[NIT];
+    const long long r0 = (long long)b * RPB;
+    T xv[NIT], xn[NIT][E], wn[NIT][E];
+    int cn[NIT][E], dg[NIT];
 #pragma unroll
     for (int it = 0; it < NIT; it++) {
-        const int i = g + it * G;
-        const bool ok = act && i < nrows;
-        const T a = x[ok ? (r0 + i) * k + j : 0];
-        xv[it] = ok ? a : (T)0;
-        const int ii = ok ? i : 0;
-        const int p0 = s_ptr[ii] - base, p1 = ok ? s_ptr[ii + 1] - base : p0;
-        pp[it] = p0;
-        pe[it] = p1;
+        const long long v = r0 + g + it * G;
+        const bool ok = v < n;
+        const long long vv = ok ? v : 0;
+        const T a = x[act ? vv * k + j : 0];
+        xv[it] = a;
+        dg[it] = ok ? edeg[vv] : 0;
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            const bool has = p0 + q < p1;
-            const int pq = has ? p0 + q : 0;
-            const int c = staged ? s_col[pq] : col[base + pq];
-            const T w = staged ? s_val[pq] : val[base + pq];
-            const T xc = x[has ? (long long)c * k + j : 0];
-            wn[it][q] = has ? w : (T)0;
-            xn[it][q] = xc;
+        for (int e = 0; e < E; e++) {
+            cn[it][e] = ecol[vv * E + e];
+            wn[it][e] = eval[vv * E + e];
         }
     }
 #pragma unroll
+    for (int it = 0; it < NIT; it++)
+#pragma unroll
+        for (int e = 0; e < E; e++) xn[it][e] = x[act ? (long long)cn[it][e] * k + j : 0];
+    const T sc = (T)pow2_scale(scale_from);
+    double dacc = 0.0;
+#pragma unroll
     for (int it = 0; it < NIT; it++) {
-        const int i = g + it * G;
+        const long long v = r0 + g + it * G;
         T acc = 0;
 #pragma unroll
-        for (int q = 0; q < 4; q++) acc += wn[it][q] * (xv[it] - xn[it][q]);
-        for (int p = pp[it] + 4; p < pe[it]; p++) {
-            const int c = staged ? s_col[p] : col[base + p];
-            const T w = staged ? s_val[p] : val[base + p];
-            acc += w * (xv[it] - x[(long long)c * k + j]);
+        for (int e = 0; e < E; e++) acc += wn[it][e] * (xv[it] - xn[it][e]);
+        if (dg[it] > E) {  // the rest of a long row
+            const int p0 = rowptr[v], p1 = rowptr[v + 1];
+            for (int p = p0 + E; p < p1; p++) acc += val[p] * (xv[it] - x[(long long)col[p] * k + j]);
         }
-        if (act && i < nrows) {
-            const long long v = r0 + i;
+        if (act && v < n) {
             acc *= sc;
             if (v == root) acc = 0;
             y[v * k + j] = acc;
@@ -784,12 +763,10 @@ __global__ void k_absmax(long long nk, const T *__restrict__ x, unsigned long lo
 
 // ============================================================= host side
 
-static int lap_rows_per_block(int kp) {
-    int r = 0;
-    KP_DISPATCH(kp, { r = LapShape<KP>::RPB; });
-    return r;
+static int lap_rows_per_block(int kp, int E = 8) {
+    return (kThreads / kp) * (E <= 4 ? LapShape<4>::NIT : LapShape<8>::NIT);
 }
-static int lap_blocks(const Dims &d) { return div_up(d.n, lap_rows_per_block(d.kp)); }
+static int lap_blocks(const Dims &d, int E = 8) { return div_up(d.n, lap_rows_per_block(d.kp, E)); }
 
 static int score_blocks(const Dims &d) { return div_up(d.m, (kThreads / d.kp) * kEdgesPerGroup); }
 static int gauss_blocks(const Dims &d) {
@@ -802,6 +779,14 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
     v.wT = a.take<T>(m);
     v.cval = a.take<T>(2 * m);
     v.pval = a.take<T>(2 * m);
+    v.eg.E = kEllG;
+    v.eg.col = a.take<int>(d.n * kEllG);
+    v.eg.val = a.take<T>(d.n * kEllG);
+    v.eg.deg = a.take<int>(d.n);
+    v.ep.E = kEllP;
+    v.ep.col = a.take<int>(d.n * kEllP);
+    v.ep.val = a.take<T>(d.n * kEllP);
+    v.ep.deg = a.take<int>(d.n);
     v.rpw = a.take<T>(d.Npad + 1);
     v.H = a.take<T>(nk);
     v.Y = a.take<T>(nk);
@@ -844,16 +829,20 @@ void start_vectors(const Dims &d, uint64_t seed, int pass, T *out, Vecs<T> &v, h
 }
 
 template <typename T>
-void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const T *x, T *y, int root,
-               const unsigned long long *scale_from, double *dot_part, hipStream_t s) {
-    int nb = lap_blocks(d);
+void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x, T *y,
+               int root, const unsigned long long *scale_from, double *dot_part, hipStream_t s) {
+    const int nb = lap_blocks(d, ell.E);
     ProfScope ps(root < 0 ? PK_SPMM_G : PK_SPMM_P,
                  4.0 * (d.n + 1) + (double)(root < 0 ? 2 * d.m : d.p_nnz) * (4 + sizeof(T)) +
                      2.0 * d.n * d.k * sizeof(T),
                  s);
     KP_DISPATCH(d.kp, {
-        hipLaunchKernelGGL((k_lap<T, KP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col, val, x, y,
-                           root, scale_from, dot_part, nb);
+        if (ell.E == kEllP)
+            hipLaunchKernelGGL((k_lap<T, KP, kEllP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col,
+                               val, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
+        else
+            hipLaunchKernelGGL((k_lap<T, KP, kEllG>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col,
+                               val, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
     });
     GR_CHECK_LAUNCH();
 }
@@ -1004,7 +993,8 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
 #define INST(T)                                                                                                  \
     template void plan_vecs<T>(Arena &, const Dims &, Vecs<T> &);                                                \
     template void start_vectors<T>(const Dims &, uint64_t, int, T *, Vecs<T> &, hipStream_t);                    \
-    template void lap_apply<T>(const Dims &, const int *, const int *, const T *, const T *, T *, int,           \
+    template void lap_apply<T>(const Dims &, const int *, const int *, const T *, const Ell<T> &, const T *, T *, \
+                               int,                                                                              \
                                const unsigned long long *, double *, hipStream_t);                               \
     template void tree_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const T *, double *,            \
                                 unsigned long long *, hipStream_t);                                              \

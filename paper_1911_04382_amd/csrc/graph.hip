@@ -570,6 +570,27 @@ void validate_graph(Topo &t, hipStream_t s) {
 }
 
 template <typename T>
+__global__ void k_ell_fill(long long n, int E, const int *__restrict__ rowptr, const int *__restrict__ col,
+                           const T *__restrict__ val, int *__restrict__ ecol, T *__restrict__ eval,
+                           int *__restrict__ edeg) {
+    GSTRIDE(v, n) {
+        const int p0 = rowptr[v], d = rowptr[v + 1] - p0;
+        edeg[v] = d;
+        for (int e = 0; e < E; e++) {
+            const bool h = e < d;
+            ecol[v * E + e] = h ? col[p0 + e] : (int)v;
+            eval[v * E + e] = h ? val[p0 + e] : (T)0;
+        }
+    }
+}
+template <typename T>
+void fill_ell(long long n, const int *rowptr, const int *col, const T *val, Ell<T> &e, hipStream_t s) {
+    hipLaunchKernelGGL(k_ell_fill<T>, dim3(grid_for(n)), dim3(256), 0, s, n, e.E, rowptr, col, val, e.col, e.val,
+                       e.deg);
+    GR_CHECK_LAUNCH();
+}
+
+template <typename T>
 void build_csr(Topo &t, Vecs<T> &v, SetupTmp &st, hipStream_t s) {
     long long n = t.n, m = t.m;
     int *in_cnt = st.n1[0], *out_cnt = st.n1[1], *in_first = st.n1[2], *out_first = st.n1[3], *tot = st.n1[4];
@@ -597,6 +618,7 @@ void build_csr(Topo &t, Vecs<T> &v, SetupTmp &st, hipStream_t s) {
     GR_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_row_finish<T>, dim3(grid_for(n)), dim3(256), 0, s, n, t.rowptr, t.ceid, t.w, v.cval, t.degG);
     GR_CHECK_LAUNCH();
+    fill_ell<T>(n, t.rowptr, t.col, v.cval, v.eg, s);
     hipLaunchKernelGGL(k_cast_w<T>, dim3(grid_for(m)), dim3(256), 0, s, m, t.w, v.wT);
     GR_CHECK_LAUNCH();
 }
@@ -815,6 +837,7 @@ void build_pcsr(Topo &t, Vecs<T> &v, hipStream_t s) {
     hipLaunchKernelGGL(k_p_fill<T>, dim3(grid_for(n)), dim3(256), 0, s, n, t.rowptr, t.col, t.ceid, t.w, t.mask,
                        t.prow, t.pcol, v.pval, t.pval64, t.degP);
     GR_CHECK_LAUNCH();
+    fill_ell<T>(n, t.prow, t.pcol, v.pval, v.ep, s);
 }
 
 void count_mask(Topo &t, const uint8_t *mask, long long out[3], hipStream_t s) {

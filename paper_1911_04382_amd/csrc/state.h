@@ -80,12 +80,27 @@ struct Topo {
     uint8_t *cand_acc = nullptr;   // [m]
 };
 
+// The first E entries of every CSR row of a Laplacian, row-major and padded with
+// the row's own column and a zero weight (so padding adds w (x_v - x_v) = 0 and
+// needs no branch); rows longer than E continue in the CSR. One SpMM row step then
+// reads its neighbours without first reading the row pointers.
+template <typename T>
+struct Ell {
+    int E = 0;
+    int *col = nullptr;  // [n*E]
+    T *val = nullptr;    // [n*E]
+    int *deg = nullptr;  // [n] CSR row length
+};
+constexpr int kEllG = 8;  // 7-point meshes and grids fit whole rows
+constexpr int kEllP = 4;  // spanning tree plus a few edges
+
 // Precision-dependent buffers.
 template <typename T>
 struct Vecs {
     T *wT = nullptr;      // [m] edge weights
     T *cval = nullptr;    // [2m] CSR(G) weights
     T *pval = nullptr;    // [2m] CSR(P) weights
+    Ell<T> eg, ep;        // padded first entries of the CSR rows of L_G and L_P
     T *rpw = nullptr;     // [Npad] 1/parent weight in layout order
     T *H = nullptr, *Y = nullptr;  // [n*kp]
     T *F = nullptr;       // [Npad*kp] subtree currents (layout order)
