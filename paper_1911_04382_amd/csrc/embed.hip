@@ -247,7 +247,7 @@ __device__ __forceinline__ void sweep_tile(
     const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
     int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
     double *__restrict__ dot_part, unsigned long long *__restrict__ absmax) {
-    constexpr int RUNS = kThreads / KP;
+    constexpr int RUNS = kSolveThreads / KP;
     constexpr int NPR = kSolveNPR;
     constexpr int TN = RUNS * NPR;
     __shared__ int s_info[3];  // level's first tile, level's tile count, logical tile
@@ -257,7 +257,7 @@ __device__ __forceinline__ void sweep_tile(
     __shared__ int s_exhs[RUNS];
     __shared__ T s_carry[KP];
     __shared__ double s_red[RUNS][KP];
-    __shared__ double s_max[kThreads / 64];
+    __shared__ double s_max[kSolveThreads / 64];
     __shared__ int s_bad;
 
     const int tid = threadIdx.x;
@@ -347,7 +347,7 @@ __device__ __forceinline__ void sweep_tile(
     // cross-level dependencies (tiles of light children / of path parents)
     {
         int bad = 0;
-        for (int d = d0 + tid; d < d1; d += kThreads) {
+        for (int d = d0 + tid; d < d1; d += kSolveThreads) {
             const unsigned *f = &done[d == d0 + tid ? dep_first : dep[d]];
             long long spin = 0;
             while (ld_agent_u32(f) != epoch) {
@@ -496,7 +496,7 @@ __device__ __forceinline__ void sweep_tile(
             __syncthreads();
             if (tid == 0) {
                 double m2 = 0.0;
-                for (int w = 0; w < kThreads / 64; w++) m2 = s_max[w] > m2 ? s_max[w] : m2;
+                for (int w = 0; w < kSolveThreads / 64; w++) m2 = s_max[w] > m2 ? s_max[w] : m2;
                 if (m2 > 0.0) atomicMax(absmax, (unsigned long long)__double_as_longlong(m2));
             }
         }
@@ -512,7 +512,7 @@ __device__ __forceinline__ void sweep_tile(
 constexpr int kTilesPerTicket = 1;
 
 template <typename T, int KP, bool UP>
-__global__ __launch_bounds__(kThreads) void k_sweep(
+__global__ __launch_bounds__(kSolveThreads) void k_sweep(
     int ntiles_total, int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm,
     const uint8_t *__restrict__ flags, const int *__restrict__ ptop, const int *__restrict__ lc_ptr,
     const int *__restrict__ lc_pos, const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F,
@@ -858,14 +858,14 @@ void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *r
         {
             // y in, subtree sums out; per node: flags, perm, light-child pointers
             ProfScope ps(PK_TREE_UP, vbytes + 13.0 * d.n, s);
-            hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nblk), dim3(kThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
+            hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
                                t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
                                (double *)nullptr, (unsigned long long *)nullptr);
         }
         {
             // subtree sums in, potentials out; per node: flags, perm, path top, 1/w
             ProfScope ps(PK_TREE_DOWN, vbytes + (9.0 + sizeof(T)) * d.n, s);
-            hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nblk), dim3(kThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
+            hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
                                t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part,
                                absmax);
         }

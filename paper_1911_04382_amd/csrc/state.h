@@ -7,7 +7,7 @@
 namespace grass {
 
 constexpr int kMaxLevels = 64;   // light depth <= log2(n) < 32; margin
-constexpr int kSolveThreads = 256;
+constexpr int kSolveThreads = 512;  // threads of a tree-sweep workgroup (one tile)
 constexpr int kSolveNPR = 16;    // nodes per run in the tree-solve scans
 constexpr int kMaxK = 64;
 
