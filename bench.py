@@ -261,7 +261,7 @@ def main():
         return
     if args.workload in ("c4", "c5"):
         # concurrent graphs need hardware queues beyond HIP's default of 4
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(16, max(4, args.workers))))
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(16, max(4, args.workers)))
 
     import torch
 

@@ -379,8 +379,8 @@ grass_opts grass_opts_default(void) {
     o.lambda_steps = 0;
     o.pcg_rtol = 1e-6;
     o.pcg_max_iters = 2000;
-    o.pcg_inner_rtol = 1e-3;
-    o.pcg_max_outer = 6;
+    o.pcg_inner_rtol = 1e-2;
+    o.pcg_max_outer = 20;
     o.precision = 32;
     o.init_mask = nullptr;
     return o;

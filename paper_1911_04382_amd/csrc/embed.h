@@ -72,8 +72,8 @@ void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride
 // Block PCG (block size k, tree preconditioner) with FP64 refinement restarts;
 // x64 and dx hold zero and red[RED_BN] the squared norms of b on entry.
 struct PcgParams {
-    double rtol = 1e-6, itol = 1e-3;
-    int max_it = 2000, max_repl = 6;
+    double rtol = 1e-6, itol = 1e-2;
+    int max_it = 2000, max_repl = 20;
 };
 template <typename T>
 SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s);

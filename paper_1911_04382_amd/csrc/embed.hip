@@ -943,9 +943,9 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     fill_T(v.dx, nk, (T)0, s);
     PcgParams pp;
     pp.rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
-    pp.itol = o.pcg_inner_rtol > 0 ? o.pcg_inner_rtol : 1e-3;
+    pp.itol = o.pcg_inner_rtol > 0 ? o.pcg_inner_rtol : 1e-2;
     pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
-    pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 6;
+    pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 20;
     SolveInfo info = block_pcg<T>(t, v, d, b, pp, s);
     fill_u32(reinterpret_cast<unsigned *>(v.u64s + U_ABSMAX), 2, 0u, s);
     hipLaunchKernelGGL(k_x64_out<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, x, v.u64s + U_ABSMAX);
