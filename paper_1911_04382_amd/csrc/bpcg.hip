@@ -307,17 +307,26 @@ __global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ 
         }
         __syncthreads();
         if (ok) {
+            // all operands first, then the arithmetic, then the stores: the
+            // elements' LDS round trips overlap instead of queueing behind each
+            // element's store
             const double rp = 1.0 / d;
+            double mv[NE], pr[NE], pc[NE];
 #pragma unroll
             for (int q = 0; q < NE; q++) {
-                const int r = er[q], c = ec[q];
-                if (r >= k) continue;
-                if (OP == SM_ALPHA) {
-                    if (r == jj) M[r * LD + c] = prow[c] * rp;
-                    else M[r * LD + c] -= pcol[r] * rp * prow[c];
-                } else if (r > jj) {
-                    M[r * LD + c] -= pcol[r] * rp * prow[c];
-                }
+                const int r = er[q] < KP ? er[q] : 0, c = ec[q];
+                mv[q] = M[r * LD + c];
+                pr[q] = prow[c];
+                pc[q] = pcol[r];
+            }
+#pragma unroll
+            for (int q = 0; q < NE; q++) {
+                const int r = er[q];
+                const double upd = mv[q] - pc[q] * rp * pr[q];
+                double nv;
+                if (OP == SM_ALPHA) nv = r == jj ? pr[q] * rp : upd;
+                else nv = r > jj ? upd : mv[q];
+                if (r < k) M[r * LD + ec[q]] = nv;
             }
         }
         __syncthreads();
