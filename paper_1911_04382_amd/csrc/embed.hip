@@ -248,7 +248,7 @@ __device__ __forceinline__ void sweep_tile(
     int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
     double *__restrict__ dot_part, unsigned long long *__restrict__ absmax) {
     constexpr int RUNS = kSolveThreads / KP;
-    constexpr int NPR = kSolveNPR;
+    constexpr int NPR = solve_npr(KP);
     constexpr int TN = RUNS * NPR;
     __shared__ int s_info[3];  // level's first tile, level's tile count, logical tile
     __shared__ T s_agg[RUNS][KP];
@@ -258,7 +258,14 @@ __device__ __forceinline__ void sweep_tile(
     __shared__ T s_carry[KP];
     __shared__ double s_red[RUNS][KP];
     __shared__ double s_max[kSolveThreads / 64];
-    __shared__ int s_bad;
+    // per-position layout data, shared by the KP lanes of a run (index: scan order)
+    __shared__ uint8_t s_fl[TN];
+    __shared__ int s_vid[TN];  // node id (-1: padding)
+    __shared__ int s_l0[TN];   // UP: first light child's position; DOWN: parent of a path top (-1: none)
+    __shared__ int s_l1[TN];   // UP: second light child's position (-1: none)
+    __shared__ int s_lcr[TN];  // UP: index in lc_pos of the third light child (rare), or -1
+    __shared__ int s_lce[TN];
+    __shared__ T s_rw[TN];     // DOWN: 1/parent weight
 
     const int tid = threadIdx.x;
     const int j = tid % KP, r = tid / KP;
@@ -280,7 +287,6 @@ __device__ __forceinline__ void sweep_tile(
             }
             acc += nt;
         }
-        s_bad = 0;
     }
     __syncthreads();
     const int lvl_first = s_info[0], ntiles = s_info[1], lt = s_info[2];
@@ -290,59 +296,51 @@ __device__ __forceinline__ void sweep_tile(
 
     // Everything that does not depend on other tiles is loaded first, so that the
     // critical path through the levels keeps a single memory hop per tile. The
-    // loads go in two unconditional rounds (clamped indices, then selects): the
-    // per-position layout data, then what it points to.
+    // layout data goes to LDS once per position (coalesced, unconditional loads
+    // with clamped indices); each thread keeps only its column's values.
     T vals[NPR];
-    int link[NPR];     // UP: first light child's position; DOWN: parent of the path top
-    int link2[NPR];    // UP: second light child's position (or -1)
-    int lcr[NPR];      // UP: index of the third light child (rare) in lc_pos, or -1
-    int lce[NPR];
-    int vid[NPR];      // node id of the position (-1: padding)
-    uint8_t fls[NPR];
-    int c0s[NPR], c1s[NPR];
-    T rw[NPR];
     const int d0 = dep_ptr[gt], d1 = dep_ptr[gt + 1];
+    const int dep_first = dep[d0 + tid < d1 ? d0 + tid : 0];
+    if (!UP) {
 #pragma unroll
-    for (int q = 0; q < NPR; q++) {
-        int sidx = r * NPR + q;
-        long long pos = p0 + (UP ? (TN - 1 - sidx) : sidx);
-        fls[q] = flags[pos];
-        vid[q] = perm[pos];
-        link2[q] = -1;
-        lcr[q] = -1;
-        lce[q] = -1;
-        if (UP) {
-            c0s[q] = lc_ptr[pos];
-            c1s[q] = lc_ptr[pos + 1];
-        } else {
-            link[q] = ptop[pos];
-            rw[q] = rpw[pos];
-            T f = F[act ? pos * k + j : 0];
+        for (int q = 0; q < NPR; q++) {
+            const long long pos = p0 + r * NPR + q;
+            const T f = F[act ? pos * k + j : 0];
             vals[q] = act ? f : (T)0;
         }
     }
-#pragma unroll
-    for (int q = 0; q < NPR; q++) {
+    for (int i = tid; i < TN; i += kSolveThreads) {
+        const long long pos = p0 + (UP ? (TN - 1 - i) : i);
+        const uint8_t fl = flags[pos];
+        s_fl[i] = fl;
+        s_vid[i] = perm[pos];
         if (UP) {
-            const int v = vid[q];
-            const bool okv = act && v >= 0;
-            T y = yin[okv ? (long long)v * k + j : 0];
-            vals[q] = okv ? y : (T)0;
-            const int c0 = c0s[q], c1 = c1s[q];
-            int l0 = lc_pos[c1 > c0 ? c0 : 0];
-            int l1 = lc_pos[c1 > c0 + 1 ? c0 + 1 : 0];
-            link[q] = c1 > c0 ? l0 : -1;
-            link2[q] = c1 > c0 + 1 ? l1 : -1;
-            if (c1 > c0 + 2) {
-                lcr[q] = c0 + 2;
-                lce[q] = c1;
-            }
+            const int c0 = lc_ptr[pos], c1 = lc_ptr[pos + 1];
+            const int l0 = lc_pos[c1 > c0 ? c0 : 0];
+            const int l1 = lc_pos[c1 > c0 + 1 ? c0 + 1 : 0];
+            s_l0[i] = c1 > c0 ? l0 : -1;
+            s_l1[i] = c1 > c0 + 1 ? l1 : -1;
+            s_lcr[i] = c1 > c0 + 2 ? c0 + 2 : -1;
+            s_lce[i] = c1;
         } else {
-            vals[q] = vals[q] * rw[q];
-            if (!(fls[q] & SEG_TOP)) link[q] = -1;
+            const int pt = ptop[pos];
+            s_l0[i] = (fl & SEG_TOP) ? pt : -1;
+            s_rw[i] = rpw[pos];
         }
     }
-    const int dep_first = dep[d0 + tid < d1 ? d0 + tid : 0];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NPR; q++) {
+        const int sidx = r * NPR + q;
+        if (UP) {
+            const int v = s_vid[sidx];
+            const bool okv = act && v >= 0;
+            const T y = yin[okv ? (long long)v * k + j : 0];
+            vals[q] = okv ? y : (T)0;
+        } else {
+            vals[q] = vals[q] * s_rw[sidx];
+        }
+    }
 
     // cross-level dependencies (tiles of light children / of path parents)
     {
@@ -364,35 +362,44 @@ __device__ __forceinline__ void sweep_tile(
 
     // the single dependent hop (all of a thread's loads in flight together:
     // clamped indices, then selects), then the run-local inclusive segmented scan
-    T hop0[NPR], hop1[NPR];
+    {
+        T h0[NPR], h1[NPR];
 #pragma unroll
-    for (int q = 0; q < NPR; q++) {
-        const bool ok0 = act && link[q] >= 0, ok1 = UP && act && link2[q] >= 0;
-        T a = ld_agent(UP ? &F[ok0 ? (long long)link[q] * k + j : 0] : &xout[ok0 ? (long long)link[q] * k + j : 0]);
-        T b = UP ? ld_agent(&F[ok1 ? (long long)link2[q] * k + j : 0]) : (T)0;
-        hop0[q] = ok0 ? a : (T)0;
-        hop1[q] = ok1 ? b : (T)0;
+        for (int q = 0; q < NPR; q++) {
+            const int sidx = r * NPR + q;
+            const int l0 = s_l0[sidx], l1 = UP ? s_l1[sidx] : -1;
+            const bool ok0 = act && l0 >= 0, ok1 = UP && act && l1 >= 0;
+            const T a = ld_agent(UP ? &F[ok0 ? (long long)l0 * k + j : 0] : &xout[ok0 ? (long long)l0 * k + j : 0]);
+            const T b = UP ? ld_agent(&F[ok1 ? (long long)l1 * k + j : 0]) : (T)0;
+            h0[q] = ok0 ? a : (T)0;
+            h1[q] = ok1 ? b : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < NPR; q++) {
+            vals[q] += h0[q];
+            vals[q] += h1[q];
+        }
     }
-    bool pre[NPR];
+    unsigned pre = 0;  // bit q: a segment starts at or before position q of this run
     bool seen = false;
     T acc = 0;
 #pragma unroll
     for (int q = 0; q < NPR; q++) {
+        const int sidx = r * NPR + q;
         T val = vals[q];
-        if (act) {
-            val += hop0[q];
-            val += hop1[q];
-            if (UP)
-                for (int c = lcr[q]; c >= 0 && c < lce[q]; c++) val += ld_agent(&F[(long long)lc_pos[c] * k + j]);
+        if (UP && act) {
+            const int c1 = s_lce[sidx];
+            for (int c = s_lcr[sidx]; c >= 0 && c < c1; c++) val += ld_agent(&F[(long long)lc_pos[c] * k + j]);
         }
-        bool start = UP ? (fls[q] & SEG_BOT) : (fls[q] & SEG_TOP);
+        const uint8_t fl = s_fl[sidx];
+        const bool start = UP ? (fl & SEG_BOT) : (fl & SEG_TOP);
         if (start) {
             acc = 0;
             seen = true;
         }
         acc += val;
         vals[q] = acc;
-        pre[q] = seen;
+        if (seen) pre |= 1u << q;
     }
     s_agg[r][j] = acc;
     if (j == 0) s_hs[r] = seen ? 1 : 0;
@@ -412,62 +419,57 @@ __device__ __forceinline__ void sweep_tile(
         const unsigned tag = (epoch << 1) | (unsigned)any;
         constexpr int TW = sizeof(T) / 4;
         tag_put<T>(&aggw[(gt * KP + j) * TW], carry, tag);
-        uint8_t f0 = flags[p0 + (UP ? (TN - 1) : 0)];
-        bool first_start = UP ? (f0 & SEG_BOT) : (f0 & SEG_TOP);
+    }
+    // carry-in: the sum of the published aggregates of the tiles back to the nearest
+    // one holding a segment start, nearest first; each step is one tagged load that
+    // gives readiness, the start bit and the value together. The summation order
+    // follows from the layout alone: deterministic.
+    if (r == 0) {
+        const uint8_t f0 = s_fl[0];
+        const bool first_start = UP ? (f0 & SEG_BOT) : (f0 & SEG_TOP);
+        constexpr int TW = sizeof(T) / 4;
         T cin = 0;
         if (!first_start) {
-            // nearest predecessor holding a segment start: each step is one tagged
-            // load that gives readiness, the start bit and the value together
-            int cnt = 0;
-            int bad = 1;  // cleared when a tile holding a segment start is reached
-            T first = 0;
             const int npred = UP ? (ntiles - 1 - lt) : lt;  // tiles before this one in scan order
+            int bad = 1;  // cleared when a tile holding a segment start is reached
             for (int back = 1; back <= npred; back++) {
-                long long pg = (long long)lvl_first + (UP ? (lt + back) : (lt - back));
+                const long long pg = (long long)lvl_first + (UP ? (lt + back) : (lt - back));
                 T val;
                 unsigned tg;
                 if (!tag_get<T>(&aggw[(pg * KP + j) * TW], epoch, val, tg)) break;
-                cnt = back;
-                first = val;
+                cin += val;
                 if (tg & 1u) {
                     bad = 0;
                     break;
                 }
             }
             if (bad && j == 0) atomicOr(devflags, DEVERR_SPIN);
-            // fixed order: from the segment-start tile towards this one
-            cin = first;
-            for (int back = cnt - 1; back >= 1; back--) {
-                long long pg = (long long)lvl_first + (UP ? (lt + back) : (lt - back));
-                T val;
-                unsigned tg;
-                if (tag_get<T>(&aggw[(pg * KP + j) * TW], epoch, val, tg)) cin += val;
-            }
         }
         s_carry[j] = cin;
     }
     __syncthreads();
 
     // final values
-    T rc = s_exhs[r] ? s_excl[r][j] : (T)(s_carry[j] + s_excl[r][j]);
+    const T rc = s_exhs[r] ? s_excl[r][j] : (T)(s_carry[j] + s_excl[r][j]);
     double dacc = 0.0, mx = 0.0;
 #pragma unroll
     for (int q = 0; q < NPR; q++) {
-        int sidx = r * NPR + q;
-        long long pos = p0 + (UP ? (TN - 1 - sidx) : sidx);
-        T out = pre[q] ? vals[q] : (T)(rc + vals[q]);
+        const int sidx = r * NPR + q;
+        const long long pos = p0 + (UP ? (TN - 1 - sidx) : sidx);
+        const T out = ((pre >> q) & 1u) ? vals[q] : (T)(rc + vals[q]);
+        const uint8_t fl = s_fl[sidx];
         if (UP) {
             if (act) {
-                if (fls[q] & SEG_TOP) st_agent(&F[pos * k + j], out);  // read by the parent's tile
+                if (fl & SEG_TOP) st_agent(&F[pos * k + j], out);  // read by the parent's tile
                 else F[pos * k + j] = out;
             }
         } else {
-            int v = vid[q];
+            const int v = s_vid[sidx];
             if (v >= 0 && act) {
-                if (fls[q] & SEG_LC) st_agent(&xout[(long long)v * k + j], out);  // a path parent's potential
+                if (fl & SEG_LC) st_agent(&xout[(long long)v * k + j], out);  // a path parent's potential
                 else xout[(long long)v * k + j] = out;
                 if (rdot) dacc += (double)rdot[(long long)v * k + j] * (double)out;
-                double ao = fabs((double)out);
+                const double ao = fabs((double)out);
                 mx = ao > mx ? ao : mx;
             }
         }

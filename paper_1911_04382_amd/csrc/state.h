@@ -8,10 +8,14 @@ namespace grass {
 
 constexpr int kMaxLevels = 64;   // light depth <= log2(n) < 32; margin
 constexpr int kSolveThreads = 512;  // threads of a tree-sweep workgroup (one tile)
-constexpr int kSolveNPR = 16;    // nodes per run in the tree-solve scans
+constexpr int kSolveNPR = 16;    // largest number of nodes per run in the tree-solve scans
 constexpr int kMaxK = 64;
 
 enum : uint8_t { SEG_TOP = 1, SEG_BOT = 2, SEG_LC = 4 };  // path top, path bottom, has light children
+
+// Nodes per run of a tree-sweep tile: a run is the KP lanes of one vector row,
+// a tile holds kSolveThreads / KP runs, so a tile covers at most 512 nodes.
+constexpr int solve_npr(int kp) { return kp < kSolveNPR ? kp : kSolveNPR; }
 
 // Sizes that fix the workspace plan.
 struct Dims {
@@ -30,7 +34,7 @@ inline Dims make_dims(long long n, long long m, int k, int prec) {
     d.k = k;
     d.kp = kpad(k);
     d.prec = prec;
-    d.TN = kSolveNPR * kSolveThreads / d.kp;
+    d.TN = solve_npr(d.kp) * kSolveThreads / d.kp;
     d.Npad = n + (long long)kMaxLevels * d.TN;
     d.ntiles = (d.Npad + d.TN - 1) / d.TN;
     return d;
