@@ -15,6 +15,7 @@
 // largest generalized eigenvalues of the tree-preconditioned system together.
 #include "embed.h"
 #include "kern.h"
+#include "lap.h"
 #include "profiler.h"
 
 namespace grass {
@@ -237,29 +238,19 @@ enum : int { T_ALPHA = 0, T_NEGALPHA = 1, T_BETA = 2, T_RINV = 3 };
 template <typename T, int KP, int OP>
 __global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ sm, T *__restrict__ outT) {
     constexpr int KK = KP * KP;
-    constexpr int W = OP == SM_ALPHA ? 3 * KP : 2 * KP;  // [G | RHS | I] or [G | I]
-    constexpr int LD = W + 1;
-    constexpr int NE = (KP * W + kThreads - 1) / kThreads;  // elements per thread
-    __shared__ double M[KP * LD];
-    __shared__ double prow[W];
-    __shared__ double pcol[KP];
-    // the reduced Gram input (and G^-1 for BETA), staged with coalesced loads
-    // before any dependent work (read in place for the widest blocks, LDS-bound)
-    constexpr bool STAGE = KP <= 32;
-    __shared__ double s_in[STAGE ? 2 * KK : 1];
-    __shared__ double s_dg;
-    __shared__ int dead[KP];
     const int tid = threadIdx.x;
     const double *in = sm + S_IN * KK;
     double *ginv = sm + S_GINV * KK;
-    if (STAGE) {
-        for (int e = tid; e < (OP == SM_NORM ? KK : 2 * KK); e += kThreads)
-            s_in[e] = OP == SM_BETA ? (e < KK ? in[e] : ginv[e - KK]) : in[e];
-        __syncthreads();
-    }
-    const double *src = STAGE ? s_in : in;
-    if (OP == SM_BETA) {
-        const double *qz = src, *gi = STAGE ? s_in + KK : ginv;
+    if constexpr (OP == SM_BETA) {
+        // Q'Z and G^-1 staged with coalesced loads (read in place for the widest
+        // blocks, LDS-bound)
+        constexpr bool STAGE = KP <= 32;
+        __shared__ double s_in[STAGE ? 2 * KK : 1];
+        if (STAGE) {
+            for (int e = tid; e < 2 * KK; e += kThreads) s_in[e] = e < KK ? in[e] : ginv[e - KK];
+            __syncthreads();
+        }
+        const double *qz = STAGE ? s_in : in, *gi = STAGE ? s_in + KK : ginv;
         for (int e = tid; e < KK; e += kThreads) {
             const int r = e / KP, c = e % KP;
             double acc = 0.0;
@@ -269,84 +260,133 @@ __global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ 
         }
         return;
     }
-    // this thread's elements of the augmented matrix (fixed for all steps)
-    int er[NE], ec[NE];
+    // Gauss-Jordan / forward elimination with the augmented matrix in registers:
+    // thread (tr, tc) owns rows tr + RG a and columns tc + CG b. A step needs only
+    // the pivot row and the pivot column, which their owners publish to LDS
+    // (double-buffered, so one barrier per step).
+    constexpr int W = OP == SM_ALPHA ? 3 * KP : 2 * KP;  // [G | RHS | I] or [G | I]
+    constexpr int CG = 32, RG = kThreads / CG;
+    constexpr int RPT = (KP + RG - 1) / RG, CPT = (W + CG - 1) / CG;
+    __shared__ double s_prow[2][W];
+    __shared__ double s_pcol[2][KP];
+    __shared__ double s_piv[KP];
+    __shared__ int s_dead[KP];
+    __shared__ double s_dg;
+    const int tr = tid / CG, tc = tid % CG;
+    double m[RPT][CPT];
+    {
+        // every operand load first (clamped indices), then the selects
+        double v1[RPT][CPT], v2[RPT][CPT];
 #pragma unroll
-    for (int q = 0; q < NE; q++) {
-        const int e = tid + kThreads * q;
-        er[q] = e < KP * W ? e / W : KP;
-        ec[q] = e % W;
-    }
+        for (int a = 0; a < RPT; a++) {
 #pragma unroll
-    for (int q = 0; q < NE; q++) {
-        const int r = er[q], c = ec[q];
-        if (r >= KP) continue;
-        double x = 0.0;
-        if (r < k) {
-            if (c < KP) x = c < k ? 0.5 * (src[r * KP + c] + src[c * KP + r]) : 0.0;
-            else if (OP == SM_ALPHA && c < 2 * KP) x = c - KP < k ? src[KK + r * KP + (c - KP)] : 0.0;
-            else x = (c - (W - KP)) == r ? 1.0 : 0.0;
+            for (int b = 0; b < CPT; b++) {
+                const int r = tr + RG * a < KP ? tr + RG * a : 0, c = tc + CG * b;
+                const int i1 = c < KP ? r * KP + c : (OP == SM_ALPHA && c < 2 * KP ? KK + r * KP + (c - KP) : 0);
+                const int i2 = c < KP ? c * KP + r : 0;
+                v1[a][b] = in[i1];
+                v2[a][b] = in[i2];
+            }
         }
-        M[r * LD + c] = x;
+#pragma unroll
+        for (int a = 0; a < RPT; a++) {
+#pragma unroll
+            for (int b = 0; b < CPT; b++) {
+                const int r = tr + RG * a, c = tc + CG * b;
+                double x;
+                if (c < KP) x = c < k ? 0.5 * (v1[a][b] + v2[a][b]) : 0.0;
+                else if (OP == SM_ALPHA && c < 2 * KP) x = c - KP < k ? v1[a][b] : 0.0;
+                else x = (c - (W - KP)) == r ? 1.0 : 0.0;
+                m[a][b] = (r < k && c < W) ? x : 0.0;
+            }
+        }
     }
     if (tid < 64) {  // largest diagonal entry, one wave
         double mx = 0.0;
-        for (int i = tid; i < k; i += 64) mx = fmax(mx, src[i * KP + i]);
+        for (int i = tid; i < k; i += 64) mx = fmax(mx, in[i * KP + i]);
         for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
         if (tid == 0) s_dg = mx;
     }
+    // owners publish row / column jj of the current matrix into buffer `buf`
+    auto publish = [&](int jj, int buf) {
+        if (tr == jj % RG) {
+            const int aa = jj / RG;
+#pragma unroll
+            for (int b = 0; b < CPT; b++) {
+                double v = 0.0;
+#pragma unroll
+                for (int a = 0; a < RPT; a++) v = a == aa ? m[a][b] : v;
+                const int c = tc + CG * b;
+                if (c < W) s_prow[buf][c] = v;
+            }
+        }
+        if (tc == jj % CG) {
+            const int bb = jj / CG;
+#pragma unroll
+            for (int a = 0; a < RPT; a++) {
+                double v = 0.0;
+#pragma unroll
+                for (int b = 0; b < CPT; b++) v = b == bb ? m[a][b] : v;
+                const int r = tr + RG * a;
+                if (r < KP) s_pcol[buf][r] = v;
+            }
+        }
+    };
+    publish(0, 0);
     __syncthreads();
     const double tol = s_dg * 1e-13;
     for (int jj = 0; jj < k; jj++) {
-        const double d = M[jj * LD + jj];
-        const bool ok = d > tol;
-        if (tid == 0) dead[jj] = ok ? 0 : 1;
+        const int buf = jj & 1;
+        const double d = s_pcol[buf][jj];
+        double pr[CPT], pc[RPT];
+#pragma unroll
+        for (int b = 0; b < CPT; b++) pr[b] = s_prow[buf][tc + CG * b < W ? tc + CG * b : 0];
+#pragma unroll
+        for (int a = 0; a < RPT; a++) pc[a] = s_pcol[buf][tr + RG * a < KP ? tr + RG * a : 0];
+        const bool ok = d > tol;  // uniform: every thread reads the same pivot
         if (ok) {
-            for (int c = tid; c < W; c += kThreads) prow[c] = M[jj * LD + c];
-            if (tid < KP) pcol[tid] = M[tid * LD + jj];
-        }
-        __syncthreads();
-        if (ok) {
-            // all operands first, then the arithmetic, then the stores: the
-            // elements' LDS round trips overlap instead of queueing behind each
-            // element's store
             const double rp = 1.0 / d;
-            double mv[NE], pr[NE], pc[NE];
 #pragma unroll
-            for (int q = 0; q < NE; q++) {
-                const int r = er[q] < KP ? er[q] : 0, c = ec[q];
-                mv[q] = M[r * LD + c];
-                pr[q] = prow[c];
-                pc[q] = pcol[r];
-            }
+            for (int a = 0; a < RPT; a++) {
+                const int r = tr + RG * a;
+                const double f = pc[a] * rp;
 #pragma unroll
-            for (int q = 0; q < NE; q++) {
-                const int r = er[q];
-                const double upd = mv[q] - pc[q] * rp * pr[q];
-                double nv;
-                if (OP == SM_ALPHA) nv = r == jj ? pr[q] * rp : upd;
-                else nv = r > jj ? upd : mv[q];
-                if (r < k) M[r * LD + ec[q]] = nv;
+                for (int b = 0; b < CPT; b++) {
+                    if (OP == SM_ALPHA) m[a][b] = r == jj ? pr[b] * rp : m[a][b] - f * pr[b];
+                    else if (r > jj) m[a][b] -= f * pr[b];
+                }
             }
         }
+        if (tid == 0) {
+            s_piv[jj] = d;
+            s_dead[jj] = ok ? 0 : 1;
+        }
+        if (jj + 1 < k) publish(jj + 1, buf ^ 1);
         __syncthreads();
     }
-    if (OP == SM_ALPHA) {
-        for (int e = tid; e < KK; e += kThreads) {
-            const int r = e / KP, c = e % KP;
-            const bool live = r < k && c < k && !dead[r];
-            const double a = live ? M[r * LD + KP + c] : 0.0;
-            outT[T_ALPHA * KK + e] = (T)a;
-            outT[T_NEGALPHA * KK + e] = (T)(-a);
-            ginv[e] = live ? M[r * LD + 2 * KP + c] : 0.0;
-        }
-    } else {
-        // rinv[i][j] = (L^-1)[j][i] / sqrt(d_j); row j of L^-1 sits in M[j][KP..2KP)
-        for (int e = tid; e < KK; e += kThreads) {
-            const int i = e / KP, j = e % KP;
-            double x = 0.0;
-            if (i < k && j < k && !dead[j]) x = M[j * LD + KP + i] / sqrt(M[j * LD + j]);
-            outT[T_RINV * KK + e] = (T)x;
+#pragma unroll
+    for (int a = 0; a < RPT; a++) {
+#pragma unroll
+        for (int b = 0; b < CPT; b++) {
+            const int r = tr + RG * a, c = tc + CG * b;
+            if (r >= KP || c < KP || c >= W) continue;
+            if (OP == SM_ALPHA) {
+                const int cc = c < 2 * KP ? c - KP : c - 2 * KP;
+                const bool live = r < k && cc < k && !s_dead[r];
+                const double x = live ? m[a][b] : 0.0;
+                const int e = r * KP + cc;
+                if (c < 2 * KP) {
+                    outT[T_ALPHA * KK + e] = (T)x;
+                    outT[T_NEGALPHA * KK + e] = (T)(-x);
+                } else {
+                    ginv[e] = x;
+                }
+            } else {
+                // rinv[i][j] = (L^-1)[j][i] / sqrt(d_j); row j of L^-1 sits in columns KP..2KP
+                const int j = r, i = c - KP;
+                const double x = (i < k && j < k && !s_dead[j]) ? m[a][b] / sqrt(s_piv[j]) : 0.0;
+                outT[T_RINV * KK + i * KP + j] = (T)x;
+            }
         }
     }
 }
@@ -431,6 +471,65 @@ __global__ __launch_bounds__(NT) void k_bgram(long long n, int k, const T *__res
     g0.flush(s_w, out);
     if (NG == 2) g1.flush(s_w, out + KK);
     if (tail_reduce(tl.part, gridDim.x, NG * KK, tl.cnt, s_w)) tail_finish<KP>(s_w, NG * KK, k, tl.op, tl.vec);
+}
+
+// Q = L_P P with the Gram matrices P'Q and P'R formed on the fly: a lane group
+// holds one row of P and of Q (KP lanes), which is the operand layout of the FP32
+// MFMA outer products, so each tile adds its rows to the two accumulators before
+// the next tile. Blocks walk several tiles each; the last block reduces the FP64
+// partials. One pass over P, Q and R instead of a product pass
+// and a three-operand Gram pass.
+template <int KP, int E>
+__global__ __launch_bounds__(kThreads) void k_lap_gram(long long n, int k, const int *__restrict__ rowptr,
+                                                       const int *__restrict__ col, const float *__restrict__ val,
+                                                       const int *__restrict__ ecol, const float *__restrict__ eval,
+                                                       const int *__restrict__ edeg, const float *__restrict__ P,
+                                                       float *__restrict__ Q, int root, const float *__restrict__ R,
+                                                       Tail<float> tl) {
+    constexpr int G = kThreads / KP, NIT = LapShape<E>::NIT, RPB = G * NIT;
+    constexpr int KK = KP * KP;
+    __shared__ double s_w[2 * KK];
+    const int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    const bool act = j < k;
+    BlockGram<float, KP, true> gq, gr;
+    gq.zero();
+    gr.zero();
+    // each XCD owns a contiguous eighth of the tiles, which its blocks sweep as one
+    // front (block q takes tiles q, q + nq, ...), so neighbour rows a few thousand
+    // rows back are still in that XCD's L2
+    const long long ntile = (n + RPB - 1) / RPB;
+    const int q = blockIdx.x >> 3, nq = gridDim.x >> 3;
+    const long long per = (ntile + 7) / 8;
+    const long long xs = std::min(ntile, (long long)(blockIdx.x & 7) * per), xe = std::min(ntile, xs + per);
+    // software pipeline: the next tile's neighbour lists are loaded while this
+    // tile's second round (issued first) is in flight
+    LapCols<E> cur, nxt;
+    if (xs + q < xe) lap_load<KP, E>((xs + q) * RPB, n, ecol, cur);
+    for (long long t = xs + q; t < xe; t += nq) {
+        const long long r0 = t * RPB;
+        LapFetch<float, E> F;
+        float rv[NIT];
+        lap_fetch<float, KP, E>(r0, n, k, eval, edeg, P, cur, F);
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const long long v = r0 + g + it * G;
+            rv[it] = R[act && v < n ? v * k + j : 0];
+        }
+        if (t + nq < xe) lap_load<KP, E>((t + nq) * RPB, n, ecol, nxt);
+        float xo[NIT], yo[NIT];
+        lap_rows<float, KP, E>(r0, n, k, rowptr, col, val, P, Q, root, 1.f, F, xo, yo);
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const bool ok = act && r0 + g + it * G < n;
+            gq.add(xo[it], yo[it]);
+            gr.add(xo[it], ok ? rv[it] : 0.f);
+        }
+        cur = nxt;
+    }
+    double *out = tl.part + (long long)blockIdx.x * 2 * KK;
+    gq.flush(s_w, out);
+    gr.flush(s_w, out + KK);
+    if (tail_reduce(tl.part, gridDim.x, 2 * KK, tl.cnt, s_w)) tail_finish<KP>(s_w, 2 * KK, k, tl.op, tl.vec);
 }
 
 // generic R -= Q alpha; per-block squared column norms of R; the last block counts
@@ -761,13 +860,17 @@ __global__ void k_copy_vec(long long nk, const T *__restrict__ a, T *__restrict_
 
 // Scratch of the tail reductions: level-0 partials and level sums (doubles) and
 // arrival counters, for the widest launch of the block PCG.
+// the product-and-Gram pass: at most this many blocks (a multiple of 8), so at most
+// that many pairs of k x k partials
+constexpr int kLapGramBlocks = 1024;
 static long long tail_grid_max(const Dims &d) {
     long long mf_rows = d.kp == 16 ? 16 : 32;
-    return std::max<long long>({(long long)gram_blocks(d.kp), (long long)vec_blocks(d), div_up(d.n, 4 * mf_rows)});
+    return std::max<long long>({(long long)gram_blocks(d.kp), (long long)kLapGramBlocks, (long long)vec_blocks(d),
+                                div_up(d.n, 4 * mf_rows)});
 }
 long long bpcg_part_doubles(const Dims &d) {
     const long long KK = (long long)d.kp * d.kp;
-    long long g = gram_blocks(d.kp), v = tail_grid_max(d);
+    long long g = std::max(gram_blocks(d.kp), kLapGramBlocks), v = tail_grid_max(d);
     return std::max(tail_items(g) * 2 * KK, tail_items(v) * d.kp) + 64;
 }
 long long bpcg_counters(const Dims &d) { return tail_items(tail_grid_max(d)) + 64; }
@@ -786,6 +889,32 @@ static void launch_gram(const Dims &d, const T *A, const T *B, const T *C, const
     else
         hipLaunchKernelGGL((k_bgram<T, KP, NG, kThreads>), dim3(gram_blocks(KP)), dim3(kThreads), 0, s, d.n, d.k, A,
                            B, C, tl);
+}
+// Q = L_P P, then P'Q and P'R: fused for FP32 blocks of 16 or 32 vectors, else a
+// product pass and a Gram pass
+template <typename T, int KP>
+static void launch_lap_gram(Topo &t, Vecs<T> &v, const Dims &d, int root, const Tail<T> &tl, hipStream_t s) {
+    if constexpr (UseMF<T, KP>::value) {
+        constexpr long long RPB = (kThreads / KP) * LapShape<kEllP>::NIT;
+        // one resident wave of blocks (each walks a range of tiles): more would
+        // leave a second, partial wave behind
+        static const int resident = [] {
+            int dev = 0, cus = 0, per = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_lap_gram<KP, kEllP>, kThreads, 0) != hipSuccess)
+                return kLapGramBlocks;
+            return std::max(8, std::min(kLapGramBlocks, cus * per / 8 * 8));
+        }();
+        const int nb = (int)std::min<long long>(resident, xcd_grid(div_up(d.n, RPB)));
+        ProfScope ps(PK_SPMM_P, 4.0 * (d.n + 1) + (double)d.p_nnz * (4 + sizeof(T)) + 3.0 * d.n * d.k * sizeof(T), s);
+        hipLaunchKernelGGL((k_lap_gram<KP, kEllP>), dim3(nb), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol, v.pval,
+                           v.ep.col, v.ep.val, v.ep.deg, v.p, v.q, root, v.r, tl);
+    } else {
+        lap_apply<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, v.q, root, nullptr, nullptr, s);
+        ProfScope ps(PK_GRAM_PQR, 3.0 * d.n * d.k * sizeof(T), s);
+        launch_gram<T, KP, 2>(d, v.p, v.q, v.r, tl, s);
+    }
 }
 template <int KP>
 static int mf_blocks(const Dims &d) {
@@ -886,12 +1015,8 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
         it++;
         bool stop = false, restart = false;
         KP_DISPATCH(d.kp, {
-            // Q = L_P P, then P'Q and P'R in one streaming pass
-            lap_apply<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, v.q, root, nullptr, nullptr, s);
-            {
-                ProfScope ps(PK_GRAM_PQR, 3.0 * nk * sizeof(T), s);
-                launch_gram<T, KP, 2>(d, v.p, v.q, v.r, tsave, s);
-            }
+            // Q = L_P P, P'Q and P'R
+            launch_lap_gram<T, KP>(t, v, d, root, tsave, s);
             launch_small<T, KP, SM_ALPHA>(d, v, s);
             launch_rupdate<T, KP>(d, v, tcheck, s);
             GR_CHECK_LAUNCH();

@@ -7,6 +7,7 @@
 // block -> XCD mapping, not MFMA.
 #include "embed.h"
 #include "kern.h"
+#include "lap.h"
 #include "profiler.h"
 
 namespace grass {
@@ -99,24 +100,6 @@ __global__ __launch_bounds__(kThreads) void k_gauss_write(long long n, int k, un
 }
 
 // ------------------------------------------------------------ Laplacian
-__device__ __forceinline__ double pow2_scale(const unsigned long long *slot) {
-    if (!slot) return 1.0;
-    double mx = __longlong_as_double((long long)*slot);
-    if (!(mx > 0.0) || !(mx < INFINITY)) return 1.0;
-    return ldexp(1.0, -ilogb(mx));
-}
-
-// y = L x for k vectors at once over the padded first E entries of each row (rows
-// longer than E finish from the CSR). The difference form y_v = sum_u w_vu (x_v -
-// x_u) keeps FP32 accurate for smooth x.
-// A lane group of KP lanes owns one row per step; all NIT rows of a group issue
-// their loads together: own values and the neighbour lists first, then the
-// neighbour rows, so a block costs two dependent memory rounds and no barrier.
-template <int E>
-struct LapShape {
-    static constexpr int NIT = E <= 4 ? 4 : 2;  // rows per lane group
-};
-
 template <typename T, int KP, int E>
 __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int *__restrict__ rowptr,
                                                   const int *__restrict__ col, const T *__restrict__ val,
@@ -130,50 +113,14 @@ __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int 
     constexpr int RPB = G * NIT;
     int b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= nblk) return;
-    const int tid = threadIdx.x;
-    const int g = tid / KP, j = tid % KP;
-    const bool act = j < k;
-    const long long r0 = (long long)b * RPB;
-    T xv[NIT], xn[NIT][E], wn[NIT][E];
-    int cn[NIT][E], dg[NIT];
-#pragma unroll
-    for (int it = 0; it < NIT; it++) {
-        const long long v = r0 + g + it * G;
-        const bool ok = v < n;
-        const long long vv = ok ? v : 0;
-        const T a = x[act ? vv * k + j : 0];
-        xv[it] = a;
-        dg[it] = ok ? edeg[vv] : 0;
-#pragma unroll
-        for (int e = 0; e < E; e++) {
-            cn[it][e] = ecol[vv * E + e];
-            wn[it][e] = eval[vv * E + e];
-        }
-    }
-#pragma unroll
-    for (int it = 0; it < NIT; it++)
-#pragma unroll
-        for (int e = 0; e < E; e++) xn[it][e] = x[act ? (long long)cn[it][e] * k + j : 0];
-    const T sc = (T)pow2_scale(scale_from);
-    double dacc = 0.0;
-#pragma unroll
-    for (int it = 0; it < NIT; it++) {
-        const long long v = r0 + g + it * G;
-        T acc = 0;
-#pragma unroll
-        for (int e = 0; e < E; e++) acc += wn[it][e] * (xv[it] - xn[it][e]);
-        if (dg[it] > E) {  // the rest of a long row
-            const int p0 = rowptr[v], p1 = rowptr[v + 1];
-            for (int p = p0 + E; p < p1; p++) acc += val[p] * (xv[it] - x[(long long)col[p] * k + j]);
-        }
-        if (act && v < n) {
-            acc *= sc;
-            if (v == root) acc = 0;
-            y[v * k + j] = acc;
-            dacc += (double)xv[it] * (double)acc;
-        }
-    }
+    const int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    T xo[NIT], yo[NIT];
+    lap_tile<T, KP, E>((long long)b * RPB, n, k, rowptr, col, val, ecol, eval, edeg, x, y, root,
+                       (T)pow2_scale(scale_from), xo, yo);
     if (dot_part) {
+        double dacc = 0.0;
+#pragma unroll
+        for (int it = 0; it < NIT; it++) dacc += (double)xo[it] * (double)yo[it];
         __shared__ double sh[G][KP];
         sh[g][j] = dacc;
         __syncthreads();
