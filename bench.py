@@ -93,8 +93,8 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
     print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4, "reps": reps}}), flush=True)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_c2_mesh100_traffic.md")
-SWEEP_SOURCES = ["embed.hip", "embed.h", "common.h", "state.h", "kern.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_kernels_c2_mesh100_traffic.md")
+PROFILED_SOURCES = ["embed.hip", "embed.h", "bpcg.hip", "lap.h", "common.h", "state.h", "kern.h"]
 
 
 def measured_traffic(kernel: str, workload: str):
@@ -106,7 +106,7 @@ def measured_traffic(kernel: str, workload: str):
     if workload != "c2" or not os.path.exists(TRAFFIC_FILE):
         return None
     h = hashlib.sha256()
-    for f in SWEEP_SOURCES:
+    for f in PROFILED_SOURCES:
         with open(os.path.join(ROOT, "paper_1911_04382_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     vals = {}
@@ -184,11 +184,12 @@ def run_serving(args, grass, torch):
     # plain-path service times (also the capacity that sets the arrival rate)
     ws = grass.workspace(max(dgs, key=lambda d: d.n + d.m), opts, "cuda:0")
     service = []
-    for dg in dgs:
+    for i, dg in enumerate(dgs):
         t0 = time.perf_counter()
         grass.grass_sparsify(ctx, dg, opts, ws=ws)
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t0)
+        log(f"plain path: request {i + 1}/{len(dgs)} (n={dg.n}) {service[-1] * 1e3:.0f} ms")
     mu = 1.0 / (sum(service) / len(service))
     rate = args.rho * mu
     rng = np.random.Generator(np.random.Philox(key=1))
@@ -205,11 +206,25 @@ def run_serving(args, grass, torch):
     srv = grass.Server(ctx, max(need * args.workers, int(args.arena_gb * (1 << 30))), workers=args.workers)
     t0 = time.perf_counter()
     tickets = []
+    seen = [0]
+
+    def progress():  # one line whenever more requests have finished
+        c = sum(1 for t in tickets if srv.poll(t)["state"] in (grass.REQ_DONE, grass.REQ_CANCELLED))
+        if c != seen[0]:
+            seen[0] = c
+            log(f"server: {c}/{len(dgs)} requests finished at t={time.perf_counter() - t0:.1f} s")
+
     for a, dg in zip(arrivals, dgs):
-        dt = t0 + a - time.perf_counter()
-        if dt > 0:
-            time.sleep(dt)
+        while True:
+            dt = t0 + a - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.5))
+            progress()
         tickets.append(srv.submit(dg, opts))
+    while seen[0] < len(dgs):
+        time.sleep(0.5)
+        progress()
     srv.wait()
     infos = [srv.poll(t) for t in tickets]
     lat_srv = [i["t_end"] - i["t_submit"] for i in infos]

@@ -482,6 +482,7 @@ __global__ __launch_bounds__(NT) void k_bgram(long long n, int k, const T *__res
 template <int KP, int E>
 __global__ __launch_bounds__(kThreads) void k_lap_gram(long long n, int k, const int *__restrict__ rowptr,
                                                        const int *__restrict__ col, const float *__restrict__ val,
+                                                       const float *__restrict__ ltail,
                                                        const int *__restrict__ ecol, const float *__restrict__ eval,
                                                        const int *__restrict__ edeg, const float *__restrict__ P,
                                                        float *__restrict__ Q, int root, const float *__restrict__ R,
@@ -517,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void k_lap_gram(long long n, int k, const
         }
         if (t + nq < xe) lap_load<KP, E>((t + nq) * RPB, n, ecol, nxt);
         float xo[NIT], yo[NIT];
-        lap_rows<float, KP, E>(r0, n, k, rowptr, col, val, P, Q, root, 1.f, F, xo, yo);
+        lap_rows<float, KP, E>(r0, n, k, rowptr, col, val, ltail, P, Q, root, 1.f, F, xo, yo);
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const bool ok = act && r0 + g + it * G < n;
@@ -908,8 +909,9 @@ static void launch_lap_gram(Topo &t, Vecs<T> &v, const Dims &d, int root, const 
         }();
         const int nb = (int)std::min<long long>(resident, xcd_grid(div_up(d.n, RPB)));
         ProfScope ps(PK_SPMM_P, 4.0 * (d.n + 1) + (double)d.p_nnz * (4 + sizeof(T)) + 3.0 * d.n * d.k * sizeof(T), s);
+        lap_long<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, s);
         hipLaunchKernelGGL((k_lap_gram<KP, kEllP>), dim3(nb), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol, v.pval,
-                           v.ep.col, v.ep.val, v.ep.deg, v.p, v.q, root, v.r, tl);
+                           v.ep.tail, v.ep.col, v.ep.val, v.ep.deg, v.p, v.q, root, v.r, tl);
     } else {
         lap_apply<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, v.q, root, nullptr, nullptr, s);
         ProfScope ps(PK_GRAM_PQR, 3.0 * d.n * d.k * sizeof(T), s);

@@ -24,6 +24,9 @@ void start_vectors(const Dims &d, uint64_t seed, int pass, T *out, Vecs<T> &v, h
 // scaling of y by the power of two that brings max|x| (u64 slot) to [1, 2), optional
 // per-block partials of x.y.
 template <typename T>
+void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x,
+              hipStream_t s);
+template <typename T>
 void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x, T *y,
                int root, const unsigned long long *scale_from, double *dot_part, hipStream_t s);
 

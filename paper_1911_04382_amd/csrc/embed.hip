@@ -103,8 +103,9 @@ __global__ __launch_bounds__(kThreads) void k_gauss_write(long long n, int k, un
 template <typename T, int KP, int E>
 __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int *__restrict__ rowptr,
                                                   const int *__restrict__ col, const T *__restrict__ val,
-                                                  const int *__restrict__ ecol, const T *__restrict__ eval,
-                                                  const int *__restrict__ edeg, const T *__restrict__ x,
+                                                  const T *__restrict__ ltail, const int *__restrict__ ecol,
+                                                  const T *__restrict__ eval, const int *__restrict__ edeg,
+                                                  const T *__restrict__ x,
                                                   T *__restrict__ y, int root,
                                                   const unsigned long long *__restrict__ scale_from,
                                                   double *__restrict__ dot_part, int nblk) {
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int 
     if (b >= nblk) return;
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;
     T xo[NIT], yo[NIT];
-    lap_tile<T, KP, E>((long long)b * RPB, n, k, rowptr, col, val, ecol, eval, edeg, x, y, root,
+    lap_tile<T, KP, E>((long long)b * RPB, n, k, rowptr, col, val, ltail, ecol, eval, edeg, x, y, root,
                        (T)pow2_scale(scale_from), xo, yo);
     if (dot_part) {
         double dacc = 0.0;
@@ -133,6 +134,11 @@ __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int 
 }
 
 // ------------------------------------------------------------ tree solve
+// A tile with more extra light-child entries (third and later per node) than
+// kHubEntries, or a node with more than kHubPerNode of them, sums them in parallel
+// rounds; otherwise each node's lane group walks its own (two dependent loads each)
+constexpr int kHubEntries = 32, kHubPerNode = 2;
+
 // Tagged words: a 32-bit payload and a 32-bit tag in one 64-bit agent-scope atomic,
 // so a reader that sees the tag it waits for also holds the data (no separate
 // flag, no store-completion wait on the writer). A double takes two words.
@@ -184,11 +190,12 @@ __device__ __forceinline__ bool tag_get(const unsigned long long *p, unsigned ep
 // outputs and stamps itself done. Every awaited tile holds a smaller ticket, so
 // it is already running; every wait is bounded. Data another tile reads inside
 // the same launch moves through agent-scope (XCD-coherent) loads and stores.
-template <typename T, int KP, bool UP>
+template <typename T, int KP, bool UP, bool HUB>
 __device__ __forceinline__ void sweep_tile(
     int tk, int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm,
     const uint8_t *__restrict__ flags,
     const int *__restrict__ ptop, const int *__restrict__ lc_ptr, const int *__restrict__ lc_pos,
+    const int *__restrict__ lc_owner,
     const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F, T *__restrict__ xout,
     unsigned long long *__restrict__ aggw, unsigned *__restrict__ done,
     const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
@@ -213,12 +220,21 @@ __device__ __forceinline__ void sweep_tile(
     __shared__ int s_lcr[TN];  // UP: index in lc_pos of the third light child (rare), or -1
     __shared__ int s_lce[TN];
     __shared__ T s_rw[TN];     // DOWN: 1/parent weight
+    // UP, tiles whose nodes have many light children (hubs): the tile's light-child
+    // entries go through LDS in rounds of CH, all runs loading at once
+    constexpr int HU = sizeof(T) == 4 ? 8 : 4, CH = RUNS * HU;
+    __shared__ T s_ev[UP && HUB ? CH : 1][KP];  // per run: partial sums of its owner segments
+    __shared__ int s_eo[UP && HUB ? CH : 1];    // owner (scan index) of each partial
+    __shared__ int s_en[UP && HUB ? RUNS : 1];  // partials per run
+    __shared__ int s_ex[4];  // UP: extra entries (third and later light children), tile's entry range, max per node
 
     const int tid = threadIdx.x;
     const int j = tid % KP, r = tid / KP;
     const unsigned epoch = epoch_ptr[0] + (UP ? 0u : 1u);
     if (tid == 0) {
         int acc = 0;
+        s_ex[0] = 0;
+        s_ex[3] = 0;
         s_info[0] = 0;
         s_info[1] = 1;
         s_info[2] = 0;
@@ -269,6 +285,12 @@ __device__ __forceinline__ void sweep_tile(
             s_l1[i] = c1 > c0 + 1 ? l1 : -1;
             s_lcr[i] = c1 > c0 + 2 ? c0 + 2 : -1;
             s_lce[i] = c1;
+            if (c1 > c0 + 2) {
+                atomicAdd(&s_ex[0], c1 - c0 - 2);
+                atomicMax(&s_ex[3], c1 - c0 - 2);
+            }
+            if (i == TN - 1) s_ex[1] = c0;  // pos == p0
+            if (i == 0) s_ex[2] = c1;       // pos == p0 + TN - 1
         } else {
             const int pt = ptop[pos];
             s_l0[i] = (fl & SEG_TOP) ? pt : -1;
@@ -327,6 +349,70 @@ __device__ __forceinline__ void sweep_tile(
             vals[q] += h1[q];
         }
     }
+    // many extra light children in this tile: per round every run loads HU entries of
+    // the tile's (contiguous) light-child range, sums them per owner segment in
+    // registers and leaves one partial per segment in LDS; each node's owner then
+    // adds one partial per run its entries span (the last segment of the first run,
+    // the first of the later ones). Fixed order: entries within a run, runs, rounds.
+    const bool hub = UP && HUB && (s_ex[0] > kHubEntries || s_ex[3] > kHubPerNode);
+    if (hub) {
+        const int ea = s_ex[1], eb = s_ex[2];
+        for (int base = ea; base < eb; base += CH) {
+            int ch[HU], ow[HU];
+#pragma unroll
+            for (int u = 0; u < HU; u++) {
+                const int e = base + r * HU + u;
+                ch[u] = lc_pos[e < eb ? e : ea];
+                ow[u] = lc_owner[e < eb ? e : ea];
+            }
+            T fv[HU];
+#pragma unroll
+            for (int u = 0; u < HU; u++) fv[u] = ld_agent(&F[act ? (long long)ch[u] * k + j : 0]);
+            int nseg = 0, cur = -1;
+            T acc = 0;
+#pragma unroll
+            for (int u = 0; u < HU; u++) {
+                const int e = base + r * HU + u;
+                // scan index of the owner (UP scans positions in reverse); -1 past the range
+                const int os = e < eb ? (int)(p0 + TN - 1 - ow[u]) : -1;
+                const int lr = os >= 0 ? s_lcr[os] : -1;
+                const T x = (lr >= 0 && e >= lr) ? fv[u] : (T)0;
+                if (u > 0 && os != cur) {
+                    s_ev[r * HU + nseg][j] = acc;
+                    if (j == 0) s_eo[r * HU + nseg] = cur;
+                    nseg++;
+                    acc = 0;
+                }
+                cur = os;
+                acc += x;
+            }
+            s_ev[r * HU + nseg][j] = acc;
+            if (j == 0) {
+                s_eo[r * HU + nseg] = cur;
+                s_en[r] = nseg + 1;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < NPR; q++) {
+                const int sidx = r * NPR + q;
+                const int lr = s_lcr[sidx];
+                if (lr >= 0) {
+                    const int lo = lr > base ? lr : base, hi = s_lce[sidx] < base + CH ? s_lce[sidx] : base + CH;
+                    if (lo < hi) {
+                        const int ra = (lo - base) / HU, rb = (hi - 1 - base) / HU;
+                        if (ra == rb) {
+                            for (int sl = 0; sl < s_en[ra]; sl++)
+                                if (s_eo[ra * HU + sl] == sidx) vals[q] += s_ev[ra * HU + sl][j];
+                        } else {
+                            vals[q] += s_ev[ra * HU + s_en[ra] - 1][j];
+                            for (int rr = ra + 1; rr <= rb; rr++) vals[q] += s_ev[rr * HU][j];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
     unsigned pre = 0;  // bit q: a segment starts at or before position q of this run
     bool seen = false;
     T acc = 0;
@@ -334,7 +420,7 @@ __device__ __forceinline__ void sweep_tile(
     for (int q = 0; q < NPR; q++) {
         const int sidx = r * NPR + q;
         T val = vals[q];
-        if (UP && act) {
+        if (UP && act && !hub) {
             const int c1 = s_lce[sidx];
             for (int c = s_lcr[sidx]; c >= 0 && c < c1; c++) val += ld_agent(&F[(long long)lc_pos[c] * k + j]);
         }
@@ -460,11 +546,11 @@ __device__ __forceinline__ void sweep_tile(
 // ticket).
 constexpr int kTilesPerTicket = 1;
 
-template <typename T, int KP, bool UP>
+template <typename T, int KP, bool UP, bool HUB>
 __global__ __launch_bounds__(kSolveThreads) void k_sweep(
     int ntiles_total, int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm,
     const uint8_t *__restrict__ flags, const int *__restrict__ ptop, const int *__restrict__ lc_ptr,
-    const int *__restrict__ lc_pos, const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F,
+    const int *__restrict__ lc_pos, const int *__restrict__ lc_owner, const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F,
     T *__restrict__ xout, unsigned long long *__restrict__ aggw, unsigned *__restrict__ done,
     const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
     int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
@@ -476,7 +562,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_sweep(
     for (int c = 0; c < kTilesPerTicket; c++) {
         const int tk = base + c;
         if (tk >= ntiles_total) break;
-        sweep_tile<T, KP, UP>(tk, nlev, lvl_tile, k, perm, flags, ptop, lc_ptr, lc_pos, rpw, yin, F, xout, aggw, done,
+        sweep_tile<T, KP, UP, HUB>(tk, nlev, lvl_tile, k, perm, flags, ptop, lc_ptr, lc_pos, lc_owner, rpw, yin, F, xout, aggw, done,
                               epoch_ptr, dep_ptr, dep, ticket, devflags, rdot, dot_part, absmax);
         __syncthreads();
     }
@@ -728,14 +814,18 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
     v.wT = a.take<T>(m);
     v.cval = a.take<T>(2 * m);
     v.pval = a.take<T>(2 * m);
-    v.eg.E = kEllG;
-    v.eg.col = a.take<int>(d.n * kEllG);
-    v.eg.val = a.take<T>(d.n * kEllG);
-    v.eg.deg = a.take<int>(d.n);
-    v.ep.E = kEllP;
-    v.ep.col = a.take<int>(d.n * kEllP);
-    v.ep.val = a.take<T>(d.n * kEllP);
-    v.ep.deg = a.take<int>(d.n);
+    // at most 2m / (kLongRow + 1) rows are longer than kLongRow
+    const int lcap = (int)std::min<long long>(n, 2 * m / (kLongRow + 1) + 1);
+    for (Ell<T> *e : {&v.eg, &v.ep}) {
+        e->E = e == &v.eg ? kEllG : kEllP;
+        e->col = a.take<int>(d.n * e->E);
+        e->val = a.take<T>(d.n * e->E);
+        e->deg = a.take<int>(d.n);
+        e->cap = lcap;
+        e->lcount = a.take<int>(1);
+        e->lrow = a.take<int>(lcap);
+        e->tail = a.take<T>((long long)lcap * d.k);
+    }
     v.rpw = a.take<T>(d.Npad + 1);
     v.H = a.take<T>(nk);
     v.Y = a.take<T>(nk);
@@ -778,6 +868,17 @@ void start_vectors(const Dims &d, uint64_t seed, int pass, T *out, Vecs<T> &v, h
 }
 
 template <typename T>
+void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x,
+              hipStream_t s) {
+    if (ell.nlong == 0) return;
+    KP_DISPATCH(d.kp, {
+        hipLaunchKernelGGL((k_lap_long<T, KP>), dim3(ell.nlong), dim3(kThreads), 0, s, d.k, ell.E, rowptr, col, val,
+                           ell.lrow, x, ell.tail);
+    });
+    GR_CHECK_LAUNCH();
+}
+
+template <typename T>
 void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x, T *y,
                int root, const unsigned long long *scale_from, double *dot_part, hipStream_t s) {
     const int nb = lap_blocks(d, ell.E);
@@ -785,13 +886,14 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
                  4.0 * (d.n + 1) + (double)(root < 0 ? 2 * d.m : d.p_nnz) * (4 + sizeof(T)) +
                      2.0 * d.n * d.k * sizeof(T),
                  s);
+    lap_long<T>(d, rowptr, col, val, ell, x, s);
     KP_DISPATCH(d.kp, {
         if (ell.E == kEllP)
             hipLaunchKernelGGL((k_lap<T, KP, kEllP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col,
-                               val, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
+                               val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
         else
             hipLaunchKernelGGL((k_lap<T, KP, kEllG>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col,
-                               val, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
+                               val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
     });
     GR_CHECK_LAUNCH();
 }
@@ -807,15 +909,22 @@ void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *r
         {
             // y in, subtree sums out; per node: flags, perm, light-child pointers
             ProfScope ps(PK_TREE_UP, vbytes + 13.0 * d.n, s);
-            hipLaunchKernelGGL((k_sweep<T, KP, true>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
-                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
+            // trees with nodes of many light children (hubs) take the variant that sums
+            // them in parallel rounds; others keep the lighter kernel
+            if (t.max_lc > 2 + kHubPerNode)
+                hipLaunchKernelGGL((k_sweep<T, KP, true, true>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
+                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
+                               (double *)nullptr, (unsigned long long *)nullptr);
+            else
+                hipLaunchKernelGGL((k_sweep<T, KP, true, false>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
+                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
                                (double *)nullptr, (unsigned long long *)nullptr);
         }
         {
             // subtree sums in, potentials out; per node: flags, perm, path top, 1/w
             ProfScope ps(PK_TREE_DOWN, vbytes + (9.0 + sizeof(T)) * d.n, s);
-            hipLaunchKernelGGL((k_sweep<T, KP, false>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
-                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part,
+            hipLaunchKernelGGL((k_sweep<T, KP, false, false>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
+                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part,
                                absmax);
         }
     });
@@ -942,6 +1051,8 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
 #define INST(T)                                                                                                  \
     template void plan_vecs<T>(Arena &, const Dims &, Vecs<T> &);                                                \
     template void start_vectors<T>(const Dims &, uint64_t, int, T *, Vecs<T> &, hipStream_t);                    \
+    template void lap_long<T>(const Dims &, const int *, const int *, const T *, const Ell<T> &, const T *,       \
+                              hipStream_t);                                                                   \
     template void lap_apply<T>(const Dims &, const int *, const int *, const T *, const Ell<T> &, const T *, T *, \
                                int,                                                                              \
                                const unsigned long long *, double *, hipStream_t);                               \

@@ -389,7 +389,7 @@ __global__ void k_layout_pad(long long N, int *__restrict__ perm, uint8_t *__res
 }
 __global__ void k_lc_count(long long n, const int *__restrict__ tptr, const int *__restrict__ tcol,
                            const int *__restrict__ parent, const int *__restrict__ heavy, const int *__restrict__ lp,
-                           int *__restrict__ lcc, uint8_t *__restrict__ flags) {
+                           int *__restrict__ lcc, uint8_t *__restrict__ flags, int *__restrict__ lcmax) {
     GSTRIDE(u, n) {
         int c = 0;
         for (int a = tptr[u]; a < tptr[u + 1]; a++) {
@@ -398,16 +398,20 @@ __global__ void k_lc_count(long long n, const int *__restrict__ tptr, const int 
         }
         lcc[lp[u]] = c;
         if (c > 0) flags[lp[u]] |= SEG_LC;
+        if (c > 2) atomicMax(lcmax, c);
     }
 }
 __global__ void k_lc_fill(long long n, const int *__restrict__ tptr, const int *__restrict__ tcol,
                           const int *__restrict__ parent, const int *__restrict__ heavy, const int *__restrict__ lp,
-                          const int *__restrict__ lc_ptr, int *__restrict__ lc_pos) {
+                          const int *__restrict__ lc_ptr, int *__restrict__ lc_pos, int *__restrict__ lc_owner) {
     GSTRIDE(u, n) {
         int o = lc_ptr[lp[u]];
         for (int a = tptr[u]; a < tptr[u + 1]; a++) {
             int v = tcol[a];
-            if (parent[v] == u && v != heavy[u]) lc_pos[o++] = lp[v];
+            if (parent[v] == u && v != heavy[u]) {
+                lc_owner[o] = lp[u];
+                lc_pos[o++] = lp[v];
+            }
         }
     }
 }
@@ -528,6 +532,8 @@ void plan_topo(Arena &a, const Dims &d, Topo &t, SetupTmp &st) {
     t.ptop = a.take<int>(d.Npad + 1);
     t.lc_ptr = a.take<int>(d.Npad + 1);
     t.lc_pos = a.take<int>(n);
+    t.lc_owner = a.take<int>(n);
+    t.lcmax = a.take<int>(1);
     t.done = a.take<unsigned>(d.ntiles);
     t.tickets = a.take<int>(2 * kMaxLevels);
     t.epoch_dev = a.take<unsigned>(4);
@@ -572,10 +578,18 @@ void validate_graph(Topo &t, hipStream_t s) {
 template <typename T>
 __global__ void k_ell_fill(long long n, int E, const int *__restrict__ rowptr, const int *__restrict__ col,
                            const T *__restrict__ val, int *__restrict__ ecol, T *__restrict__ eval,
-                           int *__restrict__ edeg) {
+                           int *__restrict__ edeg, int *__restrict__ lcount, int *__restrict__ lrow, int cap) {
     GSTRIDE(v, n) {
         const int p0 = rowptr[v], d = rowptr[v + 1] - p0;
-        edeg[v] = d;
+        int dd = d;
+        if (d > kLongRow) {  // list order is arbitrary; each row's sum does not depend on it
+            const int li = atomicAdd(lcount, 1);
+            if (li < cap) {
+                lrow[li] = (int)v;
+                dd = -(li + 1);
+            }
+        }
+        edeg[v] = dd;
         for (int e = 0; e < E; e++) {
             const bool h = e < d;
             ecol[v * E + e] = h ? col[p0 + e] : (int)v;
@@ -585,9 +599,12 @@ __global__ void k_ell_fill(long long n, int E, const int *__restrict__ rowptr, c
 }
 template <typename T>
 void fill_ell(long long n, const int *rowptr, const int *col, const T *val, Ell<T> &e, hipStream_t s) {
+    fill_i32(e.lcount, 1, 0, s);
     hipLaunchKernelGGL(k_ell_fill<T>, dim3(grid_for(n)), dim3(256), 0, s, n, e.E, rowptr, col, val, e.col, e.val,
-                       e.deg);
+                       e.deg, e.lcount, e.lrow, e.cap);
     GR_CHECK_LAUNCH();
+    e.nlong = read_i32(e.lcount, s);
+    require(e.nlong <= e.cap, GRASS_ERR_DEVICE, "long-row list exceeds its bound");
 }
 
 template <typename T>
@@ -772,12 +789,14 @@ void build_tree(Topo &t, Vecs<T> &v, const Dims &d, SetupTmp &st, hipStream_t s)
                        v.rpw, t.lc_ptr);
     hipLaunchKernelGGL(k_layout<T>, dim3(grid_for(n)), dim3(256), 0, s, n, t.head, t.off, pbase, t.heavy, t.parent,
                        t.pw, t.lp, t.perm, t.flags, t.ptop, v.rpw);
+    fill_i32(t.lcmax, 1, 0, s);
     hipLaunchKernelGGL(k_lc_count, dim3(grid_for(n)), dim3(256), 0, s, n, tptr, tcol, t.parent, t.heavy, t.lp,
-                       t.lc_ptr, t.flags);
+                       t.lc_ptr, t.flags, t.lcmax);
     GR_CHECK_LAUNCH();
+    t.max_lc = read_i32(t.lcmax, s);
     scan_excl_i32(t.lc_ptr, t.lc_ptr, t.N + 1, nullptr, t.scan, s);
     hipLaunchKernelGGL(k_lc_fill, dim3(grid_for(n)), dim3(256), 0, s, n, tptr, tcol, t.parent, t.heavy, t.lp, t.lc_ptr,
-                       t.lc_pos);
+                       t.lc_pos, t.lc_owner);
     GR_CHECK_LAUNCH();
     // per-level tile ranges and per-tile dependencies of the dataflow sweeps
     long long NT = t.N / d.TN;

@@ -78,8 +78,8 @@ __device__ __forceinline__ void lap_fetch(long long r0, long long n, int k, cons
 template <typename T, int KP, int E>
 __device__ __forceinline__ void lap_rows(long long r0, long long n, int k, const int *__restrict__ rowptr,
                                          const int *__restrict__ col, const T *__restrict__ val,
-                                         const T *__restrict__ x, T *__restrict__ y, int root, T sc,
-                                         const LapFetch<T, E> &F, T (&xo)[LapShape<E>::NIT],
+                                         const T *__restrict__ ltail, const T *__restrict__ x, T *__restrict__ y,
+                                         int root, T sc, const LapFetch<T, E> &F, T (&xo)[LapShape<E>::NIT],
                                          T (&yo)[LapShape<E>::NIT]) {
     constexpr int G = kThreads / KP;
     constexpr int NIT = LapShape<E>::NIT;
@@ -91,7 +91,9 @@ __device__ __forceinline__ void lap_rows(long long r0, long long n, int k, const
         T acc = 0;
 #pragma unroll
         for (int e = 0; e < E; e++) acc += F.wn[it][e] * (F.xv[it] - F.xn[it][e]);
-        if (v < n && F.dg[it] > E) {  // the rest of a long row
+        if (F.dg[it] < 0) {  // a long row: the rest was summed by lap_long
+            acc += act ? ltail[(long long)(-F.dg[it] - 1) * k + j] : (T)0;
+        } else if (v < n && F.dg[it] > E) {  // the rest of a row of at most kLongRow entries
             const int p0 = rowptr[v], p1 = rowptr[v + 1];
             for (int p = p0 + E; p < p1; p++) acc += val[p] * (F.xv[it] - x[(long long)col[p] * k + j]);
         }
@@ -109,7 +111,8 @@ __device__ __forceinline__ void lap_rows(long long r0, long long n, int k, const
 template <typename T, int KP, int E>
 __device__ __forceinline__ void lap_tile(long long r0, long long n, int k, const int *__restrict__ rowptr,
                                          const int *__restrict__ col, const T *__restrict__ val,
-                                         const int *__restrict__ ecol, const T *__restrict__ eval,
+                                         const T *__restrict__ ltail, const int *__restrict__ ecol,
+                                         const T *__restrict__ eval,
                                          const int *__restrict__ edeg, const T *__restrict__ x, T *__restrict__ y,
                                          int root, T sc, T (&xo)[LapShape<E>::NIT], T (&yo)[LapShape<E>::NIT]) {
     constexpr int G = kThreads / KP;
@@ -133,7 +136,46 @@ __device__ __forceinline__ void lap_tile(long long r0, long long n, int k, const
     for (int it = 0; it < LapShape<E>::NIT; it++)
 #pragma unroll
         for (int e = 0; e < E; e++) F.xn[it][e] = x[act ? (long long)L.cn[it][e] * k + j : 0];
-    lap_rows<T, KP, E>(r0, n, k, rowptr, col, val, x, y, root, sc, F, xo, yo);
+    lap_rows<T, KP, E>(r0, n, k, rowptr, col, val, ltail, x, y, root, sc, F, xo, yo);
+}
+
+// The entries past E of the long rows (ell list lrow), one workgroup per row: lane
+// groups take every G-th entry, and the group sums are added in group order, so
+// the result does not depend on timing. tail[li*k + j] feeds lap_rows.
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_lap_long(int k, int E, const int *__restrict__ rowptr,
+                                                       const int *__restrict__ col, const T *__restrict__ val,
+                                                       const int *__restrict__ lrow, const T *__restrict__ x,
+                                                       T *__restrict__ tail) {
+    constexpr int G = kThreads / KP, U = 4;
+    __shared__ T s[G][KP];
+    const int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    const bool act = j < k;
+    const int v = lrow[blockIdx.x];
+    const int p0 = rowptr[v] + E, p1 = rowptr[v + 1];
+    const T xv = x[act ? (long long)v * k + j : 0];
+    T acc = 0;
+    for (int p = p0 + g; p < p1; p += G * U) {
+        int c[U];
+        T w[U], xn[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int q = p + u * G;
+            c[u] = col[q < p1 ? q : p0];
+            w[u] = val[q < p1 ? q : p0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) xn[u] = x[act ? (long long)c[u] * k + j : 0];
+#pragma unroll
+        for (int u = 0; u < U; u++) acc += p + u * G < p1 ? w[u] * (xv - xn[u]) : (T)0;
+    }
+    s[g][j] = acc;
+    __syncthreads();
+    if (g == 0 && act) {
+        T t = 0;
+        for (int q = 0; q < G; q++) t += s[q][j];
+        tail[(long long)blockIdx.x * k + j] = t;
+    }
 }
 
 }  // namespace grass

@@ -66,6 +66,9 @@ struct Topo {
     int *ptop = nullptr;           // [Npad]
     int *lc_ptr = nullptr;         // [Npad+1]
     int *lc_pos = nullptr;         // [n]
+    int *lc_owner = nullptr;       // [n] position of each entry's parent
+    int *lcmax = nullptr;          // [1] most light children of one node (when more than 2)
+    int max_lc = 0;                // host copy
     // tile scan state
     unsigned *done = nullptr;      // [ntiles] outputs written (epoch stamp)
     int *tickets = nullptr;        // [2*kMaxLevels]: sweep tickets
@@ -93,10 +96,18 @@ struct Ell {
     int E = 0;
     int *col = nullptr;  // [n*E]
     T *val = nullptr;    // [n*E]
-    int *deg = nullptr;  // [n] CSR row length
+    int *deg = nullptr;  // [n] CSR row length, or -(1 + index in lrow) for a long row
+    // rows longer than kLongRow: their entries past E are summed by a workgroup each
+    // before the product (tail[li*k + j]), so one long row does not hold up a tile
+    int cap = 0;           // capacity of lrow
+    int nlong = 0;         // host copy of the count, set when the ELL is filled
+    int *lcount = nullptr; // [1] device counter
+    int *lrow = nullptr;   // [cap] row ids
+    T *tail = nullptr;     // [cap*k]
 };
 constexpr int kEllG = 8;  // 7-point meshes and grids fit whole rows
 constexpr int kEllP = 4;  // spanning tree plus a few edges
+constexpr int kLongRow = 32;  // rows longer than this get a workgroup of their own
 
 // Precision-dependent buffers.
 template <typename T>

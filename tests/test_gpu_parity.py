@@ -68,6 +68,9 @@ def test_start_vectors(ctx, precision):
     np.testing.assert_allclose(h, ref, rtol=tol, atol=tol * np.abs(ref).max())
 
 
+LONG_ROW = 32  # rows of L_G / L_P with more entries take the long-row path
+
+
 def _norm_err(heat, ref, off):
     s = heat / heat[off].max()
     r = ref / ref[off].max()
@@ -80,6 +83,8 @@ EMBED_CASES = [
     ("mesh_k32", lambda: G.mesh3d(14, 13, 12, weights=(G.W_LOGUNIFORM10, -3, 3), seed=1), 32, 2, 32),
     ("powergrid_t3", lambda: G.grid2d_longrange(70, seed=2), 16, 3, 32),
     ("ba_k16", lambda: G.ba(3000, seed=5), 16, 2, 32),
+    # hubs: rows of L_G beyond the long-row bound, tree nodes with dozens of light children
+    ("ba_hubs_k16", lambda: G.ba(12000, seed=5), 16, 2, 32),
     ("rgg_k5", lambda: G.rgg(2500, seed=7), 5, 2, 32),
 ]
 
@@ -90,6 +95,11 @@ def test_embed_tree_pass(ctx, case):
     g = mk()
     say("embed tree pass:", name, g.n, g.m, k, t, prec)
     tmask = O.max_spanning_tree(g)
+    if "hubs" in name:  # the case covers long rows of L_G and tiles of many light children
+        inT = tmask != 0
+        degT = np.bincount(np.concatenate([g.src[inT], g.dst[inT]]), minlength=g.n)
+        degG = np.bincount(np.concatenate([g.src, g.dst]), minlength=g.n)
+        assert degT.max() > 36 and (degG > LONG_ROW).sum() > 0
     dg = grass.to_device(g, DEV)
     pm = torch.as_tensor(tmask).to(DEV)
     opts = grass.make_opts(k=k, t=t, precision=prec, seed=11)
@@ -106,16 +116,28 @@ def test_embed_tree_pass(ctx, case):
     assert st["m_off"] == off.sum()
 
 
-@pytest.mark.parametrize("prec", [64, 32])
-def test_embed_with_added_edges_pcg(ctx, prec):
-    g = G.grid2d(40, 40, seed=3) if prec == 64 else G.mesh3d(16, 15, 14, weights=(G.W_LOGUNIFORM10, -3, 3), seed=4)
-    k = 8 if prec == 64 else 16
-    say("embed PCG pass:", g.name, prec)
+PCG_CASES = [
+    ("grid_fp64", lambda: G.grid2d(40, 40, seed=3), 8, 64),
+    ("mesh_fp32", lambda: G.mesh3d(16, 15, 14, weights=(G.W_LOGUNIFORM10, -3, 3), seed=4), 16, 32),
+    # hubs: L_P rows past the long-row bound (their tails summed by a workgroup each)
+    ("ba_hubs_fp32", lambda: G.ba(12000, seed=5), 16, 32),
+]
+
+
+@pytest.mark.parametrize("case", PCG_CASES, ids=[c[0] for c in PCG_CASES])
+def test_embed_with_added_edges_pcg(ctx, case):
+    name, mk, k, prec = case
+    g = mk()
+    say("embed PCG pass:", name, g.n, g.m, prec)
     tmask = O.max_spanning_tree(g)
     r0 = O.embed(g, tmask, k=k, t=2, seed=0)
     th = O.theta(100.0, r0.stats["lambda_min"], r0.stats["lambda_max"], 2)
     P, acc, _ = O.filter_select(g, r0.heat, tmask, th, r0.stats["heat_max"], sim_hops=1, budget=max(1, g.n // 100))
     assert acc > 0
+    if name.startswith("ba"):
+        inP = P != 0
+        degP = np.bincount(np.concatenate([g.src[inP], g.dst[inP]]), minlength=g.n)
+        assert (degP > LONG_ROW).sum() > 0  # the case covers long rows of L_P
     dg = grass.to_device(g, DEV)
     pm = torch.as_tensor(P).to(DEV)
     # FP64 runs solve L_P to the oracle's own tolerance; FP32 runs use the default 1e-6
