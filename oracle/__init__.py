@@ -106,6 +106,8 @@ def lib():
         L.orc_tree_solve.restype = None
         L.orc_pcg.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, i32, vp, vp, dbl, i32, vp]
         L.orc_pcg.restype = i32
+        L.orc_sdd_solve.argtypes = [i64, i64, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, dbl, i32, dbl, vp]
+        L.orc_sdd_solve.restype = i32
         L.orc_philox4x64_10.argtypes = [vp, vp, vp]
         L.orc_philox4x64_10.restype = None
         L.orc_gauss_vectors.argtypes = [i64, i32, u64, i64, vp]
@@ -203,6 +205,25 @@ def pcg(g, inP, tree, b, rtol=1e-12, maxit=100000):
     P = np.ascontiguousarray(inP, dtype=np.uint8)
     it = lib().orc_pcg(g.n, g.m, _p(s), _p(d), _p(w), _p(P), _p(parent), _p(pw), _p(order), k, _p(b), _p(x),
                        rtol, maxit, ctypes.byref(res))
+    return x, it, res.value
+
+
+def sdd_solve(g, p_mask, b, rtol=1e-3, maxit=1000, rtol_inner=1e-12):
+    """Sec. V-E: PCG on the grounded L_G preconditioned by the sparsifier P.
+    p_mask uses the sparsify convention (1 = spanning-tree edge, 2 = added edge);
+    P is the tree alone when no edge is marked 2. Returns (x, outer iterations
+    (largest over the columns), largest final ||r|| / ||b||)."""
+    s, d, w = _edges(g)
+    mask = np.asarray(p_mask)
+    tree = root_tree(g, (mask == 1).astype(np.uint8))
+    parent, pw, order = tree
+    inP = np.ascontiguousarray(mask != 0, dtype=np.uint8)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    k = 1 if b.ndim == 1 else b.shape[1]
+    x = np.empty_like(b)
+    res = ctypes.c_double(0.0)
+    it = lib().orc_sdd_solve(g.n, g.m, _p(s), _p(d), _p(w), _p(inP), int(not (mask == 2).any()), _p(parent),
+                             _p(pw), _p(order), k, _p(b), _p(x), rtol, maxit, rtol_inner, ctypes.byref(res))
     return x, it, res.value
 
 

@@ -288,6 +288,85 @@ int orc_pcg(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const 
     return worst;
 }
 
+/* ======================================= SDD solver with the sparsifier (Sec. V-E)
+ * The paper's solver experiment: preconditioned CG on L_G, the preconditioner
+ * being the sparsifier P, stopped at ||L_G x - b|| <= rtol ||b||. L_G is grounded
+ * at the root like every solve here (row and column of the root removed, x[root]
+ * = 0). The preconditioner z = L_P^+ r is the tree solve when P is the spanning
+ * tree, else the PCG above to rtol_inner (1e-12: exact for this purpose), so
+ * plain CG coefficients apply. One recurrence per right-hand side; returns the
+ * largest outer iteration count, *resid the largest final ||r|| / ||b||. */
+int orc_sdd_solve(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                  const uint8_t *inP, int p_is_tree, const int64_t *parent, const double *pw,
+                  const int64_t *order, int k, const double *b, double *x, double rtol, int maxit,
+                  double rtol_inner, double *resid) {
+    int64_t root = order[0];
+    double *r = (double *)malloc((size_t)n * sizeof(double));
+    double *z = (double *)malloc((size_t)n * sizeof(double));
+    double *p = (double *)malloc((size_t)n * sizeof(double));
+    double *q = (double *)malloc((size_t)n * sizeof(double));
+    double *xc = (double *)malloc((size_t)n * sizeof(double));
+    int worst = 0;
+    double worst_res = 0.0;
+    for (int j = 0; j < k; j++) {
+        for (int64_t v = 0; v < n; v++) {
+            r[v] = b[(size_t)v * k + j];
+            xc[v] = 0.0;
+        }
+        r[root] = 0.0;
+        double bnorm = 0.0;
+        for (int64_t v = 0; v < n; v++) bnorm += r[v] * r[v];
+        bnorm = sqrt(bnorm);
+        int it = 0;
+        double rn = bnorm;
+        if (bnorm > 0.0) {
+            if (p_is_tree)
+                orc_tree_solve(n, parent, pw, order, 1, r, z);
+            else
+                orc_pcg(n, m, src, dst, w, inP, parent, pw, order, 1, r, z, rtol_inner, 100000, NULL);
+            memcpy(p, z, (size_t)n * sizeof(double));
+            double rz = 0.0;
+            for (int64_t v = 0; v < n; v++) rz += r[v] * z[v];
+            while (it < maxit) {
+                it++;
+                orc_laplacian_apply(n, m, src, dst, w, NULL, 1, p, q);
+                q[root] = 0.0;
+                double pq = 0.0;
+                for (int64_t v = 0; v < n; v++) pq += p[v] * q[v];
+                double alpha = rz / pq;
+                for (int64_t v = 0; v < n; v++) {
+                    xc[v] += alpha * p[v];
+                    r[v] -= alpha * q[v];
+                }
+                rn = 0.0;
+                for (int64_t v = 0; v < n; v++) rn += r[v] * r[v];
+                rn = sqrt(rn);
+                if (rn <= rtol * bnorm) break;
+                if (p_is_tree)
+                    orc_tree_solve(n, parent, pw, order, 1, r, z);
+                else
+                    orc_pcg(n, m, src, dst, w, inP, parent, pw, order, 1, r, z, rtol_inner, 100000, NULL);
+                double rz_new = 0.0;
+                for (int64_t v = 0; v < n; v++) rz_new += r[v] * z[v];
+                double beta = rz_new / rz;
+                rz = rz_new;
+                for (int64_t v = 0; v < n; v++) p[v] = z[v] + beta * p[v];
+            }
+        }
+        for (int64_t v = 0; v < n; v++) x[(size_t)v * k + j] = xc[v];
+        if (it > worst) worst = it;
+        double rel = bnorm > 0.0 ? rn / bnorm : 0.0;
+        if (rel > worst_res) worst_res = rel;
+    }
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(xc);
+    if (resid) *resid = worst_res;
+    return worst;
+}
+
 /* ======================================================= random vectors (eq. 28) */
 
 /* Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy

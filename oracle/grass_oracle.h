@@ -46,6 +46,10 @@ void orc_tree_solve(int64_t n, const int64_t *parent, const double *pw, const in
 int orc_pcg(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w, const uint8_t *inP,
             const int64_t *parent, const double *pw, const int64_t *order, int k, const double *b, double *x,
             double rtol, int maxit, double *resid);
+int orc_sdd_solve(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                  const uint8_t *inP, int p_is_tree, const int64_t *parent, const double *pw,
+                  const int64_t *order, int k, const double *b, double *x, double rtol, int maxit,
+                  double rtol_inner, double *resid);
 void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);
 void orc_gauss_vectors(int64_t n, int k, uint64_t seed, int64_t pass, double *h0);
 int orc_embed(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w, const uint8_t *inP,

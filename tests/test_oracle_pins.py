@@ -238,6 +238,30 @@ def test_pcg_dense_and_iteration_bound():
             assert it == 1
 
 
+def test_sdd_solve_dense_and_iteration_bound():
+    """Sec. V-E solver: PCG on L_G with the sparsifier as preconditioner. Pinned to
+    the dense pseudo-inverse, and to the rank argument: with P = G minus s edges,
+    L_P^+ L_G - I has rank <= s, so CG stops within s + 1 steps (exact arithmetic)."""
+    g = G.random_connected(40, 50, seed=12)
+    tmask = O.max_spanning_tree(g)
+    b = np.random.default_rng(5).standard_normal((g.n, 2))
+    b -= b.mean(0)
+    xd = np.linalg.pinv(dense_laplacian(g)) @ b
+    x, it, res = O.sdd_solve(g, tmask, b, rtol=1e-13)
+    np.testing.assert_allclose(x - x.mean(0), xd, rtol=1e-9, atol=1e-9 * np.abs(xd).max())
+    assert res <= 1e-13 and it <= g.n
+    off = np.flatnonzero(tmask == 0)
+    for s_count in (0, 1, 3, 5):
+        mask = tmask.copy()
+        mask[off] = 2
+        mask[off[:s_count]] = 0
+        x, it, res = O.sdd_solve(g, mask, b, rtol=1e-12)
+        np.testing.assert_allclose(x - x.mean(0), xd, rtol=1e-9, atol=1e-9 * np.abs(xd).max())
+        assert it <= s_count + 2, (s_count, it)
+        if s_count == 0:
+            assert it == 1
+
+
 # ------------------------------------------- P5/P6: power iteration and heat
 @pytest.mark.parametrize("g", SMALL[:5], ids=lambda g: g.name)
 @pytest.mark.parametrize("t", [1, 2, 3])
