@@ -227,6 +227,21 @@ def sdd_solve(g, p_mask, b, rtol=1e-3, maxit=1000, rtol_inner=1e-12):
     return x, it, res.value
 
 
+def partition(g, p_mask, steps=5, seed=0, rtol=1e-3, maxit=1000):
+    """Sec. V-F: a few inverse power iterations for the Fiedler vector of L_G, each
+    step solving L_G x = u with the sparsifier-preconditioned PCG of sdd_solve,
+    then removing the mean and normalizing; the sign cut gives the two parts.
+    u0 is the Philox Gaussian vector of eq. (28) (pass 0, mean removed). Returns
+    (u, side) with side[v] = 1 where u[v] >= 0."""
+    u = gauss_vectors(g.n, 1, seed, 0)[:, 0].copy()
+    u /= np.linalg.norm(u)
+    for _ in range(steps):
+        x, _, _ = sdd_solve(g, p_mask, u, rtol=rtol, maxit=maxit)
+        x = x - x.mean()
+        u = x / np.linalg.norm(x)
+    return u, (u >= 0).astype(np.uint8)
+
+
 def philox4x64_10(ctr, key):
     c = np.asarray(ctr, dtype=np.uint64)
     kk = np.asarray(key, dtype=np.uint64)

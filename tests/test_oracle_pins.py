@@ -262,6 +262,34 @@ def test_sdd_solve_dense_and_iteration_bound():
             assert it == 1
 
 
+def test_partition_converges_to_dense_fiedler_vector():
+    """Sec. V-F partitioner: enough inverse power steps give the eigenvector of the
+    smallest nonzero eigenvalue of L_G (dense eigh), whatever the preconditioner."""
+    g = G.grid2d(9, 7, seed=4)
+    w, V = np.linalg.eigh(dense_laplacian(g))
+    f = V[:, 1]
+    assert w[2] - w[1] > 1e-3 * w[1]  # a simple Fiedler value
+    tmask = O.max_spanning_tree(g)
+    u, side = O.partition(g, tmask, steps=300, seed=2, rtol=1e-12)
+    assert abs(float(u @ f)) >= 1 - 1e-9
+    np.testing.assert_array_equal(side, (u >= 0).astype(np.uint8))
+
+
+def test_partition_splits_two_clusters_at_the_bridge():
+    """Two 12-cliques joined by one weak edge: the sign cut is the two cliques."""
+    n1 = 12
+    edges = [(a, b) for a in range(n1) for b in range(a + 1, n1)]
+    edges += [(n1 + a, n1 + b) for a in range(n1) for b in range(a + 1, n1)]
+    edges.append((n1 - 1, n1))
+    edges.sort()
+    src = np.array([e[0] for e in edges], np.int32)
+    dst = np.array([e[1] for e in edges], np.int32)
+    w = np.where((src == n1 - 1) & (dst == n1), 1e-3, 1.0)
+    g = G.Graph(name="two_cliques", n=2 * n1, src=src, dst=dst, w=w)
+    u, side = O.partition(g, O.max_spanning_tree(g), steps=6, seed=1, rtol=1e-12)
+    assert len(set(side[:n1])) == 1 and len(set(side[n1:])) == 1 and side[0] != side[-1]
+
+
 # ------------------------------------------- P5/P6: power iteration and heat
 @pytest.mark.parametrize("g", SMALL[:5], ids=lambda g: g.name)
 @pytest.mark.parametrize("t", [1, 2, 3])
