@@ -167,6 +167,77 @@ def run_batch(args, grass, torch):
     print(json.dumps(line), flush=True)
 
 
+def run_solve(args, grass, torch):
+    """Sec. V-E on C2: sparsify, then solve L_G x = b for 16 seeded random right-hand
+    sides to ||L_G x - b|| <= 1e-3 ||b|| with the sparsifier as the preconditioner,
+    and with the spanning tree alone (the paper's N with and without sparsification)."""
+    from paper_1911_04382_amd import graphs as G
+
+    g = G.config_c2(100)
+    dg = grass.to_device(g, "cuda:0")
+    ctx = grass.Context(0)
+    res = grass.grass_sparsify(ctx, dg, grass.make_opts(k=32, t=2, sigma2=100.0, precision=32))
+    torch.cuda.synchronize()
+    log(f"solve: sparsifier with {res.summary['added_edges']} added edges, kappa {res.summary['kappa']:.1f}")
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    b = torch.randn(g.n, 16, generator=gen, dtype=torch.float32)
+    b = (b - b.mean(0)).to("cuda:0")
+    sopts = grass.make_opts(k=16, precision=32, pcg_rtol=1e-1)  # inner L_P solves inside flexible CG
+    out = {}
+    for label, mask in (("sparsifier", res.mask), ("tree", None)):
+        ws = grass.solve_workspace(dg, sopts)
+        rc, x, info = grass.grass_solve(ctx, dg, b, sopts, p_mask=mask, rtol=1e-3, max_iters=5000, ws=ws)
+        torch.cuda.synchronize()
+        info["status"] = rc
+        info["edges_per_node"] = (g.n - 1 + info["added_edges"]) / g.n
+        out[label] = info
+        log(f"  {label}: {info['iters']} iterations ({info['inner_iters']} inner), {info['ms']:.1f} ms, "
+            f"residual {info['resid']:.2e}")
+    line = {"metric": "PCG on L_G to ||r|| <= 1e-3 ||b|| with the sparsifier as the preconditioner (Sec. V-E)",
+            "value": out["sparsifier"]["ms"], "unit": "ms (16 right-hand sides)", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "C2 graph (100^3 mesh, 10^U(-3,3)), sparsifier from grass_sparsify at sigma^2=100, "
+                                   "16 seeded Gaussian right-hand sides (mean removed), inner L_P solves to 1e-1"},
+            "sparsifier": out["sparsifier"], "tree": out["tree"],
+            "iteration_ratio_tree_over_sparsifier": out["tree"]["iters"] / max(1, out["sparsifier"]["iters"])}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def run_partition(args, grass, torch):
+    """Sec. V-F on a synthetic 500 x 500 mesh with random weights: sign cut after 5
+    inverse power steps with the sparsifier-preconditioned solver at 1e-3 against
+    the cut from tight solves (1e-6), as the paper compares with a direct solver
+    (both FP64: on this mesh FP32 cannot hold a 1e-3 residual)."""
+    from paper_1911_04382_amd import graphs as G
+
+    g = G.grid2d(500, 500, seed=11)
+    dg = grass.to_device(g, "cuda:0")
+    ctx = grass.Context(0)
+    res = grass.grass_sparsify(ctx, dg, grass.make_opts(k=16, t=2, sigma2=100.0, precision=32))
+    torch.cuda.synchronize()
+    log(f"partition: sparsifier with {res.summary['added_edges']} added edges")
+    rc1, u1, s1, fast = grass.grass_partition(ctx, dg, grass.make_opts(precision=64, seed=5, pcg_rtol=1e-1),
+                                              p_mask=res.mask, steps=5, rtol=1e-3)
+    log(f"  1e-3 done: {fast}")
+    log("  tight solves (1e-6) ...")
+    rc2, u2, s2, tight = grass.grass_partition(ctx, dg, grass.make_opts(precision=64, seed=5, pcg_rtol=1e-2),
+                                               p_mask=res.mask, steps=5, rtol=1e-6)
+    torch.cuda.synchronize()
+    diff = float((s1 != s2).float().mean())
+    cos = abs(float((u1.double() * u2).sum()))
+    log(f"  1e-3: {fast}; 1e-6: {tight}; sides differ on {100 * diff:.3f}% of nodes, |cos| {cos:.6f}")
+    line = {"metric": "spectral partitioning with the sparsifier: share of nodes whose sign differs from tight "
+                      "solves (Sec. V-F)", "value": 100 * diff, "unit": "% of nodes", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "500x500 4-neighbour mesh, U[1,10), sparsifier at sigma^2=100 (k=16, t=2), "
+                                   "5 inverse power steps"},
+            "fast": dict(fast, status=rc1), "tight": dict(tight, status=rc2), "abs_cos": cos,
+            "speedup_fast_vs_tight": tight["ms"] / fast["ms"]}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def run_serving(args, grass, torch):
     """C5: a Poisson stream of sparsify requests on preferential-attachment graphs.
     Plain path: one request at a time in arrival order on one stream. Server:
@@ -286,6 +357,10 @@ def main():
         return run_batch(args, grass, torch)
     if args.workload == "c5":
         return run_serving(args, grass, torch)
+    if args.workload == "solve":
+        return run_solve(args, grass, torch)
+    if args.workload == "partition":
+        return run_partition(args, grass, torch)
 
     g, cfg, desc = workload(args.workload)
     for kv in args.opt:

@@ -211,6 +211,59 @@ grass_status grass_select(grass_ctx *ctx, const grass_graph *g, uint8_t *p_mask,
                           const void *heat, double lambda_max, double lambda_min, grass_pass_stats *stats,
                           void *scores, void *workspace, size_t ws_bytes, void *stream);
 
+/* The sparsifier as a preconditioner (Sec. V-E): solve L_G x = b for k = opts->k
+ * right-hand sides by preconditioned CG, the preconditioner being L_P^+ for the
+ * subgraph P of p_mask (device uint8 [m], 1 = spanning-tree edge, 2 = added edge,
+ * as grass_sparsify writes it; NULL = the maximum-weight spanning tree alone).
+ * L_P^+ is applied exactly (tree solve) when P is a tree, else by the block PCG of
+ * the power iterations to opts->pcg_rtol, with flexible CG coefficients. The system
+ * is grounded at node 0 (row and column removed, x[0] = 0); b should sum to zero
+ * per column. b, x: device n x k row-major, float32 or float64 per
+ * opts->precision, distinct (b is not modified). Stops when every column has
+ * ||r|| <= rtol ||b|| for the residual recomputed from x (the recurrence restarts
+ * from it, at most 5 times, when working-precision drift leaves it above rtol) or
+ * after max_iters outer iterations. opts->pcg_rtol sets the accuracy of each
+ * preconditioner solve (1e-2 is enough inside the flexible recurrence; tighter
+ * costs inner iterations). info (host, optional):
+ * outer iterations (the paper's N), inner block-PCG iterations, the largest
+ * ||b - L_G x|| / ||b|| recomputed from x, wall time, edges of P beyond the tree.
+ * Returns GRASS_NOT_CONVERGED (x valid) when rtol was not reached. Workspace:
+ * grass_solve_workspace_bytes (or NULL: the context allocates). */
+typedef struct {
+    int32_t iters;
+    int64_t inner_iters;
+    double resid;
+    double ms;
+    int64_t added_edges;
+} grass_solve_info;
+size_t grass_solve_workspace_bytes(int64_t n, int64_t m, const grass_opts *opts);
+grass_status grass_solve(grass_ctx *ctx, const grass_graph *g, const uint8_t *p_mask, const grass_opts *opts,
+                         const void *b, void *x, double rtol, int32_t max_iters, grass_solve_info *info,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/* Spectral partitioning with the sparsifier (Sec. V-F): `steps` inverse power
+ * iterations u <- (L_G^+ u - mean(.)) / ||.|| from the start vector of eq. (28)
+ * (opts->seed, pass 0, one vector), each solve by grass_solve's method to rtol with
+ * the subgraph of p_mask (NULL = the spanning tree) as the preconditioner; the two
+ * parts are the sign cut of the approximate Fiedler vector u. fiedler: device [n],
+ * float32 or float64 per opts->precision (unit norm, mean zero); side: device
+ * uint8 [n], 1 where u >= 0. opts->k is ignored (one vector); outer solves stop
+ * after opts->pcg_max_iters iterations (1000 when 0). info (host, optional): outer
+ * and inner iterations summed over the steps, the largest solve residual, wall
+ * time. GRASS_NOT_CONVERGED (outputs valid) when a solve missed rtol. Workspace:
+ * grass_partition_workspace_bytes (or NULL: the context allocates). */
+typedef struct {
+    int32_t steps;
+    int64_t outer_iters;
+    int64_t inner_iters;
+    double resid;
+    double ms;
+} grass_partition_info;
+size_t grass_partition_workspace_bytes(int64_t n, int64_t m, const grass_opts *opts);
+grass_status grass_partition(grass_ctx *ctx, const grass_graph *g, const uint8_t *p_mask, const grass_opts *opts,
+                             int32_t steps, double rtol, void *fiedler, uint8_t *side, grass_partition_info *info,
+                             void *workspace, size_t ws_bytes, void *stream);
+
 /* Start vectors h_0 of eq. (28): n x k row-major, float32 or float64 per precision,
  * Philox4x64-10 Gaussians with each vector's mean removed. out: device. */
 grass_status grass_start_vectors(grass_ctx *ctx, int64_t n, int32_t k, uint64_t seed, int32_t pass,

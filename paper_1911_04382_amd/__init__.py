@@ -55,6 +55,26 @@ class grass_pass_stats(ctypes.Structure):
         return {f[0].rstrip("_"): getattr(self, f[0]) for f in self._fields_}
 
 
+class grass_solve_info(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int32), ("inner_iters", ctypes.c_int64), ("resid", ctypes.c_double),
+        ("ms", ctypes.c_double), ("added_edges", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+class grass_partition_info(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int32), ("outer_iters", ctypes.c_int64), ("inner_iters", ctypes.c_int64),
+        ("resid", ctypes.c_double), ("ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
 class grass_summary(ctypes.Structure):
     _fields_ = [
         ("lambda_max", ctypes.c_double), ("lambda_min", ctypes.c_double), ("kappa", ctypes.c_double),
@@ -123,6 +143,16 @@ def load_library(path: str = LIB_PATH):
     L.grass_select.argtypes = [vp, ctypes.POINTER(grass_graph), vp, ctypes.POINTER(grass_opts), vp, dbl, dbl,
                                ctypes.POINTER(grass_pass_stats), vp, vp, ctypes.c_size_t, vp]
     L.grass_select.restype = st
+    L.grass_solve_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(grass_opts)]
+    L.grass_solve_workspace_bytes.restype = ctypes.c_size_t
+    L.grass_solve.argtypes = [vp, ctypes.POINTER(grass_graph), vp, ctypes.POINTER(grass_opts), vp, vp, dbl, i32,
+                              ctypes.POINTER(grass_solve_info), vp, ctypes.c_size_t, vp]
+    L.grass_solve.restype = st
+    L.grass_partition_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(grass_opts)]
+    L.grass_partition_workspace_bytes.restype = ctypes.c_size_t
+    L.grass_partition.argtypes = [vp, ctypes.POINTER(grass_graph), vp, ctypes.POINTER(grass_opts), i32, dbl, vp, vp,
+                                  ctypes.POINTER(grass_partition_info), vp, ctypes.c_size_t, vp]
+    L.grass_partition.restype = st
     L.grass_start_vectors.argtypes = [vp, i64, i32, u64, i32, i32, vp, vp]
     L.grass_start_vectors.restype = st
     L.grass_gram.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp]
@@ -427,6 +457,48 @@ def grass_embed(ctx: Context, g: DeviceGraph, p_mask, opts: grass_opts, pass_=0,
                                   pass_, ctypes.c_void_p(heat.data_ptr()), ctypes.byref(st), wsp, wsb,
                                   _stream_ptr(stream)))
     return heat, st.as_dict()
+
+
+def solve_workspace(g: DeviceGraph, opts: grass_opts, device="cuda:0"):
+    """A uint8 device tensor of grass_solve_workspace_bytes()."""
+    torch = _torch()
+    nbytes = load_library().grass_solve_workspace_bytes(g.n, g.m, ctypes.byref(opts))
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def grass_solve(ctx: Context, g: DeviceGraph, b, opts: grass_opts, p_mask=None, rtol=1e-3, max_iters=1000, ws=None,
+                stream=None):
+    """Sec. V-E: x with L_G x = b (grounded at node 0), preconditioned by L_P^+ for the
+    subgraph of p_mask (None: the spanning tree). b: device n x opts.k tensor of the
+    working precision. Returns (status, x, info dict)."""
+    torch = _torch()
+    b = b.contiguous()
+    x = torch.empty_like(b)
+    info = grass_solve_info()
+    gc = g.c()
+    wsp, wsb = _ws_args(ws)
+    rc = ctx.check(ctx.lib.grass_solve(ctx.h, ctypes.byref(gc),
+                                       None if p_mask is None else ctypes.c_void_p(p_mask.data_ptr()),
+                                       ctypes.byref(opts), ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                       float(rtol), int(max_iters), ctypes.byref(info), wsp, wsb, _stream_ptr(stream)))
+    return rc, x, info.as_dict()
+
+
+def grass_partition(ctx: Context, g: DeviceGraph, opts: grass_opts, p_mask=None, steps=5, rtol=1e-3, ws=None,
+                    stream=None):
+    """Sec. V-F: (status, fiedler vector, side (uint8, 1 where u >= 0), info dict)."""
+    torch = _torch()
+    u = torch.empty(g.n, dtype=torch.float64 if opts.precision == 64 else torch.float32, device=g.src.device)
+    side = torch.empty(g.n, dtype=torch.uint8, device=g.src.device)
+    info = grass_partition_info()
+    gc = g.c()
+    wsp, wsb = _ws_args(ws)
+    rc = ctx.check(ctx.lib.grass_partition(ctx.h, ctypes.byref(gc),
+                                           None if p_mask is None else ctypes.c_void_p(p_mask.data_ptr()),
+                                           ctypes.byref(opts), int(steps), float(rtol), ctypes.c_void_p(u.data_ptr()),
+                                           ctypes.c_void_p(side.data_ptr()), ctypes.byref(info), wsp, wsb,
+                                           _stream_ptr(stream)))
+    return rc, u, side, info.as_dict()
 
 
 def grass_select(ctx: Context, g: DeviceGraph, p_mask, opts: grass_opts, heat, lambda_max, lambda_min, ws=None,

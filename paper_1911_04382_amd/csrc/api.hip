@@ -45,6 +45,44 @@ size_t plan_bytes(long long n, long long m, int k, int prec) {
     return a.off + 256;
 }
 
+size_t plan_solve_bytes(long long n, long long m, int k, int prec) {
+    Arena a;
+    a.dry = true;
+    if (prec == 64) {
+        Session<double> S;
+        plan_session<double>(a, n, m, k, prec, S);
+        SddVecs<double> B;
+        plan_sdd<double>(a, S.d, B);
+    } else {
+        Session<float> S;
+        plan_session<float>(a, n, m, k, prec, S);
+        SddVecs<float> B;
+        plan_sdd<float>(a, S.d, B);
+    }
+    return a.off + 256;
+}
+
+size_t plan_partition_bytes(long long n, long long m, int prec) {
+    Arena a;
+    a.dry = true;
+    if (prec == 64) {
+        Session<double> S;
+        plan_session<double>(a, n, m, 1, prec, S);
+        SddVecs<double> B;
+        plan_sdd<double>(a, S.d, B);
+        PartVecs<double> P;
+        plan_part<double>(a, S.d, P);
+    } else {
+        Session<float> S;
+        plan_session<float>(a, n, m, 1, prec, S);
+        SddVecs<float> B;
+        plan_sdd<float>(a, S.d, B);
+        PartVecs<float> P;
+        plan_part<float>(a, S.d, P);
+    }
+    return a.off + 256;
+}
+
 void check_opts(const grass_opts &o) {
     require(o.k >= 1 && o.k <= kMaxK, GRASS_ERR_INVALID, "k must be in 1..64");
     require(o.t >= 1 && o.t <= 64, GRASS_ERR_INVALID, "t must be in 1..64");
@@ -236,6 +274,71 @@ grass_status sparsify_impl(grass_ctx *ctx, const grass_graph &g, const grass_opt
         sm.pcg_iters = pcg_total;
     }
     return kappa <= o.sigma2 ? GRASS_OK : GRASS_NOT_CONVERGED;
+}
+
+// Sec. V-E: L_G x = b with the subgraph of p_mask (or the spanning tree) as the
+// preconditioner.
+template <typename T>
+grass_status solve_impl(grass_ctx *ctx, const grass_graph &g, const uint8_t *p_mask, const grass_opts &o,
+                        const T *b, T *x, double rtol, int maxit, grass_solve_info *info, void *ws, size_t ws_bytes,
+                        hipStream_t s) {
+    size_t need = plan_solve_bytes(g.n, g.m, o.k, o.precision);
+    Arena a = bind_arena(ctx, ws, ws_bytes, need);
+    Session<T> S;
+    plan_session<T>(a, g.n, g.m, o.k, o.precision, S);
+    SddVecs<T> B;
+    plan_sdd<T>(a, S.d, B);
+    setup<T>(S, g, p_mask, true, s);
+    long long cnt[3];
+    count_mask(S.t, S.t.mask, cnt, s);
+    require(cnt[2] == 0, GRASS_ERR_INVALID, "p_mask values must be 0, 1 or 2");
+    auto t0 = std::chrono::steady_clock::now();
+    SddInfo si = sdd_solve<T>(S.t, S.v, S.d, B, b, x, rtol, maxit, cnt[1] == 0, o, s);
+    GR_HIP(hipStreamSynchronize(s));
+    check_device_flags(S.t, s);
+    if (info) {
+        info->iters = si.iters;
+        info->inner_iters = si.inner;
+        info->resid = si.resid;
+        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        info->added_edges = cnt[1];
+    }
+    return si.resid <= rtol ? GRASS_OK : GRASS_NOT_CONVERGED;
+}
+
+// Sec. V-F: the sign cut of an approximate Fiedler vector from inverse power steps
+// through the sparsifier-preconditioned solver (one vector: k = 1).
+template <typename T>
+grass_status partition_impl(grass_ctx *ctx, const grass_graph &g, const uint8_t *p_mask, const grass_opts &o,
+                            int steps, double rtol, T *u, uint8_t *side, grass_partition_info *info, void *ws,
+                            size_t ws_bytes, hipStream_t s) {
+    size_t need = plan_partition_bytes(g.n, g.m, o.precision);
+    Arena a = bind_arena(ctx, ws, ws_bytes, need);
+    Session<T> S;
+    plan_session<T>(a, g.n, g.m, 1, o.precision, S);
+    SddVecs<T> B;
+    plan_sdd<T>(a, S.d, B);
+    PartVecs<T> P;
+    plan_part<T>(a, S.d, P);
+    setup<T>(S, g, p_mask, true, s);
+    long long cnt[3];
+    count_mask(S.t, S.t.mask, cnt, s);
+    require(cnt[2] == 0, GRASS_ERR_INVALID, "p_mask values must be 0, 1 or 2");
+    grass_opts o1 = o;
+    o1.k = 1;
+    auto t0 = std::chrono::steady_clock::now();
+    PartInfo pi = partition_run<T>(S.t, S.v, S.d, B, P, u, side, steps, rtol, o.pcg_max_iters > 0 ? o.pcg_max_iters : 1000,
+                                   cnt[1] == 0, o1, s);
+    GR_HIP(hipStreamSynchronize(s));
+    check_device_flags(S.t, s);
+    if (info) {
+        info->steps = steps;
+        info->outer_iters = pi.outer;
+        info->inner_iters = pi.inner;
+        info->resid = pi.resid;
+        info->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return pi.resid <= rtol ? GRASS_OK : GRASS_NOT_CONVERGED;
 }
 
 template <typename T>
@@ -440,6 +543,58 @@ grass_status grass_embed(grass_ctx *ctx, const grass_graph *g, const uint8_t *p_
                                       ws_bytes, s);
         return embed_impl<float>(ctx, *g, p_mask, *opts, pass, static_cast<float *>(heat), stats, workspace, ws_bytes,
                                  s);
+    });
+}
+
+size_t grass_solve_workspace_bytes(int64_t n, int64_t m, const grass_opts *opts) {
+    grass_opts o = opts ? *opts : grass_opts_default();
+    if (n < 2 || m < 1 || o.k < 1 || o.k > kMaxK || (o.precision != 32 && o.precision != 64)) return 0;
+    return plan_solve_bytes(n, m, o.k, o.precision);
+}
+
+grass_status grass_solve(grass_ctx *ctx, const grass_graph *g, const uint8_t *p_mask, const grass_opts *opts,
+                         const void *b, void *x, double rtol, int32_t max_iters, grass_solve_info *info,
+                         void *workspace, size_t ws_bytes, void *stream) {
+    return guarded(ctx, [&]() -> grass_status {
+        check_graph(g);
+        require(opts != nullptr, GRASS_ERR_INVALID, "opts are required");
+        check_opts(*opts);
+        require(b != nullptr && x != nullptr && b != x, GRASS_ERR_INVALID, "b and x must be distinct device arrays");
+        require(rtol > 0.0 && rtol < 1.0, GRASS_ERR_INVALID, "rtol must be in (0, 1)");
+        require(max_iters >= 1, GRASS_ERR_INVALID, "max_iters must be >= 1");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (opts->precision == 64)
+            return solve_impl<double>(ctx, *g, p_mask, *opts, static_cast<const double *>(b), static_cast<double *>(x),
+                                      rtol, max_iters, info, workspace, ws_bytes, s);
+        return solve_impl<float>(ctx, *g, p_mask, *opts, static_cast<const float *>(b), static_cast<float *>(x), rtol,
+                                 max_iters, info, workspace, ws_bytes, s);
+    });
+}
+
+size_t grass_partition_workspace_bytes(int64_t n, int64_t m, const grass_opts *opts) {
+    grass_opts o = opts ? *opts : grass_opts_default();
+    if (n < 2 || m < 1 || (o.precision != 32 && o.precision != 64)) return 0;
+    return plan_partition_bytes(n, m, o.precision);
+}
+
+grass_status grass_partition(grass_ctx *ctx, const grass_graph *g, const uint8_t *p_mask, const grass_opts *opts,
+                             int32_t steps, double rtol, void *fiedler, uint8_t *side, grass_partition_info *info,
+                             void *workspace, size_t ws_bytes, void *stream) {
+    return guarded(ctx, [&]() -> grass_status {
+        check_graph(g);
+        require(opts != nullptr, GRASS_ERR_INVALID, "opts are required");
+        grass_opts o = *opts;
+        o.k = 1;
+        check_opts(o);
+        require(fiedler != nullptr && side != nullptr, GRASS_ERR_INVALID, "fiedler and side are required");
+        require(steps >= 1 && steps <= 1000, GRASS_ERR_INVALID, "steps must be in 1..1000");
+        require(rtol > 0.0 && rtol < 1.0, GRASS_ERR_INVALID, "rtol must be in (0, 1)");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (o.precision == 64)
+            return partition_impl<double>(ctx, *g, p_mask, o, steps, rtol, static_cast<double *>(fiedler), side, info,
+                                          workspace, ws_bytes, s);
+        return partition_impl<float>(ctx, *g, p_mask, o, steps, rtol, static_cast<float *>(fiedler), side, info,
+                                     workspace, ws_bytes, s);
     });
 }
 

@@ -24,11 +24,13 @@ void start_vectors(const Dims &d, uint64_t seed, int pass, T *out, Vecs<T> &v, h
 // scaling of y by the power of two that brings max|x| (u64 slot) to [1, 2), optional
 // per-block partials of x.y.
 template <typename T>
-void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x,
-              hipStream_t s);
-template <typename T>
 void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x, T *y,
                int root, const unsigned long long *scale_from, double *dot_part, hipStream_t s);
+// The entries past E of the rows longer than kLongRow, one workgroup per row, into
+// ell.tail (lap_apply calls it; callers of the product kernels directly must too).
+template <typename T>
+void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x,
+              hipStream_t s);
 
 // Grounded tree solve x = L_T^+ y (x[root] = 0): up-sweep then down-sweep over the
 // heavy-light levels. x may alias y. Optional fused outputs of the down-sweep:
@@ -94,5 +96,45 @@ void block_gram(const Dims &d, const T *A, const T *B, double *part, int *cnt, d
 // max|x| of an n x k block into the absmax slot
 template <typename T>
 void absmax_of(const Dims &d, const T *x, unsigned long long *slot, hipStream_t s);
+
+// Sec. V-E: L_G x = b for k right-hand sides by flexible preconditioned CG (one
+// recurrence per column, FP64 coefficients), the preconditioner being the exact tree
+// solve (tree_only) or the L_P solve above. Grounded at the root like every solve.
+template <typename T>
+struct SddVecs {
+    T *r = nullptr, *z0 = nullptr, *z1 = nullptr, *p = nullptr, *q = nullptr;  // n x k each
+    double *gram = nullptr;  // [4 * kp * kp]
+    double *sc = nullptr;    // [4 * kMaxK]: (unused), r'z, alpha, beta
+};
+template <typename T>
+void plan_sdd(Arena &a, const Dims &d, SddVecs<T> &B);
+struct SddInfo {
+    int iters = 0;           // outer iterations
+    long long inner = 0;     // inner block-PCG iterations over all preconditioner solves
+    double resid = 0.0;      // max over columns of ||b - L_G x|| / ||b|| (working precision, recomputed)
+    int restarts = 0;        // recurrences restarted from the recomputed residual
+};
+template <typename T>
+SddInfo sdd_solve(Topo &t, Vecs<T> &v, const Dims &d, SddVecs<T> &B, const T *b, T *x, double rtol, int maxit,
+                  bool tree_only, const grass_opts &o, hipStream_t s);
+
+// Sec. V-F: `steps` inverse power iterations u <- (L_G^+ u - mean) / norm from the
+// eq. (28) start vector (k = 1), each solve by sdd_solve to rtol; side = sign cut
+// (1 where u >= 0). u: device [n] working precision; side: device [n].
+template <typename T>
+struct PartVecs {
+    T *x = nullptr;           // [n] solve output
+    double *part = nullptr;   // per-block sums
+    double *stats = nullptr;  // [2]: sum, sum of squares
+};
+template <typename T>
+void plan_part(Arena &a, const Dims &d, PartVecs<T> &P);
+struct PartInfo {
+    long long outer = 0, inner = 0;
+    double resid = 0.0;
+};
+template <typename T>
+PartInfo partition_run(Topo &t, Vecs<T> &v, const Dims &d, SddVecs<T> &B, PartVecs<T> &P, T *u, uint8_t *side,
+                       int steps, double rtol, int maxit, bool tree_only, const grass_opts &o, hipStream_t s);
 
 }  // namespace grass

@@ -439,19 +439,50 @@ __device__ __forceinline__ void sweep_tile(
     __syncthreads();
 
     // cross-run exclusive scan per column, tile aggregate, publication, look-back
-    if (r == 0) {
-        T carry = 0;
-        int any = 0;
-        for (int rr = 0; rr < RUNS; rr++) {
-            s_excl[rr][j] = carry;
-            if (j == 0) s_exhs[rr] = any;
-            if (s_hs[rr]) carry = s_agg[rr][j];
-            else carry += s_agg[rr][j];
-            any |= s_hs[rr];
+    if constexpr (RUNS <= 32) {
+        // few runs (k >= 16): one thread per column walks them
+        if (r == 0) {
+            T carry = 0;
+            int any = 0;
+            for (int rr = 0; rr < RUNS; rr++) {
+                s_excl[rr][j] = carry;
+                if (j == 0) s_exhs[rr] = any;
+                if (s_hs[rr]) carry = s_agg[rr][j];
+                else carry += s_agg[rr][j];
+                any |= s_hs[rr];
+            }
+            const unsigned tag = (epoch << 1) | (unsigned)any;
+            constexpr int TW = sizeof(T) / 4;
+            tag_put<T>(&aggw[(gt * KP + j) * TW], carry, tag);
         }
-        const unsigned tag = (epoch << 1) | (unsigned)any;
-        constexpr int TW = sizeof(T) / 4;
-        tag_put<T>(&aggw[(gt * KP + j) * TW], carry, tag);
+    } else {
+        // many runs (small k): log-step segmented scan across runs, in place, pairs
+        // (value, segment-start seen) combined as (b.f ? b.v : a.v + b.v, a.f | b.f)
+        T vv = s_agg[r][j];
+        int ff = s_hs[r];
+        for (int dd = 1; dd < RUNS; dd <<= 1) {
+            T pv = 0;
+            int pf = 0;
+            if (r >= dd) {
+                pv = s_agg[r - dd][j];
+                pf = s_hs[r - dd];
+            }
+            __syncthreads();
+            if (r >= dd && !ff) vv = pv + vv;
+            ff |= pf;
+            s_agg[r][j] = vv;
+            if (j == 0) s_hs[r] = ff;
+            __syncthreads();
+        }
+        // exclusive value of run r: the inclusive one of run r - 1
+        s_excl[r][j] = r > 0 ? s_agg[r - 1][j] : (T)0;
+        if (j == 0) s_exhs[r] = r > 0 ? s_hs[r - 1] : 0;
+        if (r == 0) {
+            const int any = s_hs[RUNS - 1];
+            const unsigned tag = (epoch << 1) | (unsigned)any;
+            constexpr int TW = sizeof(T) / 4;
+            tag_put<T>(&aggw[(gt * KP + j) * TW], s_agg[RUNS - 1][j], tag);
+        }
     }
     // carry-in: the sum of the published aggregates of the tiles back to the nearest
     // one holding a segment start, nearest first; each step is one tagged load that
@@ -1002,6 +1033,8 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     PcgParams pp;
     pp.rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
     pp.itol = o.pcg_inner_rtol > 0 ? o.pcg_inner_rtol : 1e-2;
+    // a target looser than the inner phase's reduction ends that phase at the target
+    pp.itol = std::max(pp.itol, pp.rtol);
     pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
     pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 20;
     SolveInfo info = block_pcg<T>(t, v, d, b, pp, s);

@@ -20,7 +20,10 @@ def test_library_exports_every_declared_symbol():
 def test_header_declares_the_boundary_calls():
     declared = set(grass.exported_symbols_declared_in_header())
     for name in ("grass_create", "grass_destroy", "grass_last_error", "grass_opts_default", "grass_workspace_bytes",
-                 "grass_sparsify", "grass_spanning_tree", "grass_embed", "grass_select", "grass_start_vectors"):
+                 "grass_sparsify", "grass_spanning_tree", "grass_embed", "grass_select", "grass_start_vectors",
+                 "grass_sparsify_batch", "grass_batch_workspace_bytes", "grass_server_create", "grass_server_submit",
+                 "grass_solve", "grass_solve_workspace_bytes", "grass_partition",
+                 "grass_partition_workspace_bytes"):
         assert name in declared
 
 
@@ -63,3 +66,13 @@ def test_binding_fails_loudly_without_library(tmp_path):
             mod.load_library(str(tmp_path / "missing.so"))
     finally:
         mod._lib = saved
+
+
+def test_solve_workspace_covers_the_sparsify_workspace():
+    lib = grass.load_library()
+    o = grass.make_opts(k=16)
+    for n, m in ((1000, 3000), (100000, 400000)):
+        a = lib.grass_workspace_bytes(n, m, ctypes.byref(o))
+        b = lib.grass_solve_workspace_bytes(n, m, ctypes.byref(o))
+        assert b > a > 0
+    assert lib.grass_solve_workspace_bytes(1, 0, ctypes.byref(o)) == 0
