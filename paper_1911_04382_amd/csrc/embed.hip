@@ -6,6 +6,7 @@
 // HBM traffic (or latency), so the design work is coalescing, fusion and the
 // block -> XCD mapping, not MFMA.
 #include "embed.h"
+#include "gram.h"
 #include "kern.h"
 #include "lap.h"
 #include "profiler.h"
@@ -190,7 +191,7 @@ __device__ __forceinline__ bool tag_get(const unsigned long long *p, unsigned ep
 // outputs and stamps itself done. Every awaited tile holds a smaller ticket, so
 // it is already running; every wait is bounded. Data another tile reads inside
 // the same launch moves through agent-scope (XCD-coherent) loads and stores.
-template <typename T, int KP, bool UP, bool HUB>
+template <typename T, int KP, bool UP, bool HUB, bool GRAM>
 __device__ __forceinline__ void sweep_tile(
     int tk, int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm,
     const uint8_t *__restrict__ flags,
@@ -200,7 +201,8 @@ __device__ __forceinline__ void sweep_tile(
     unsigned long long *__restrict__ aggw, unsigned *__restrict__ done,
     const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
     int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
-    double *__restrict__ dot_part, unsigned long long *__restrict__ absmax) {
+    double *__restrict__ dot_part, unsigned long long *__restrict__ absmax, int ntiles_total,
+    const T *__restrict__ qz_q, double *__restrict__ qz_part, int *__restrict__ qz_cnt, double *__restrict__ qz_out) {
     constexpr int RUNS = kSolveThreads / KP;
     constexpr int NPR = solve_npr(KP);
     constexpr int TN = RUNS * NPR;
@@ -536,12 +538,36 @@ __device__ __forceinline__ void sweep_tile(
                 const double ao = fabs((double)out);
                 mx = ao > mx ? ao : mx;
             }
+            if constexpr (GRAM) vals[q] = (v >= 0 && act) ? out : (T)0;
         }
     }
     // completion stamp: all of this tile's stores are done before it is published
     wait_mem();
     __syncthreads();
     if (tid == 0) st_agent_u32(&done[gt], epoch);
+
+    if constexpr (!UP && GRAM) {
+        // after the stamp, off the path through the levels: this tile's share of the
+        // Gram Q'x (rows of Q gathered by node id), reduced over all tiles in ticket
+        // order
+        constexpr int KK = KP * KP;
+        __shared__ double s_gw[KK];
+        T qv[NPR];
+#pragma unroll
+        for (int q = 0; q < NPR; q++) {
+            const int v = s_vid[r * NPR + q];
+            const bool ok = v >= 0 && act;
+            const T x = qz_q[ok ? (long long)v * k + j : 0];
+            qv[q] = ok ? x : (T)0;
+        }
+        BlockGram<T, KP> gq;
+        gq.zero();
+#pragma unroll
+        for (int q = 0; q < NPR; q++) gq.add(qv[q], vals[q]);
+        gq.flush(s_gw, qz_part + (long long)tk * KK);
+        if (tail_reduce(qz_part, ntiles_total, KK, qz_cnt, s_gw, tk))
+            for (int e = tid; e < KK; e += kSolveThreads) qz_out[e] = s_gw[e];
+    }
 
     if (!UP) {
         if (dot_part) {
@@ -569,34 +595,24 @@ __device__ __forceinline__ void sweep_tile(
     }
 }
 
-// Tiles per ticket. A workgroup may take a chunk of consecutive tickets with one
-// atomic and process its tiles in order (still deadlock-free: a tile waits only
-// for smaller tickets). Chunks make dependents wait behind the other tiles of a
-// chunk, which stretches the critical path through the levels, so tickets are
-// kept few by large tiles instead (the single counter serialises about 7 ns per
-// ticket).
-constexpr int kTilesPerTicket = 1;
-
-template <typename T, int KP, bool UP, bool HUB>
+template <typename T, int KP, bool UP, bool HUB, bool GRAM>
 __global__ __launch_bounds__(kSolveThreads) void k_sweep(
     int ntiles_total, int nlev, const int *__restrict__ lvl_tile, int k, const int *__restrict__ perm,
     const uint8_t *__restrict__ flags, const int *__restrict__ ptop, const int *__restrict__ lc_ptr,
-    const int *__restrict__ lc_pos, const int *__restrict__ lc_owner, const T *__restrict__ rpw, const T *__restrict__ yin, T *__restrict__ F,
-    T *__restrict__ xout, unsigned long long *__restrict__ aggw, unsigned *__restrict__ done,
-    const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
-    int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
-    double *__restrict__ dot_part, unsigned long long *__restrict__ absmax) {
-    __shared__ int s_base;
-    if (threadIdx.x == 0) s_base = atomicAdd(ticket, kTilesPerTicket);
+    const int *__restrict__ lc_pos, const int *__restrict__ lc_owner, const T *__restrict__ rpw,
+    const T *__restrict__ yin, T *__restrict__ F, T *__restrict__ xout, unsigned long long *__restrict__ aggw,
+    unsigned *__restrict__ done, const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr,
+    const int *__restrict__ dep, int *__restrict__ ticket, unsigned *__restrict__ devflags,
+    const T *__restrict__ rdot, double *__restrict__ dot_part, unsigned long long *__restrict__ absmax,
+    const T *__restrict__ qz_q, double *__restrict__ qz_part, int *__restrict__ qz_cnt, double *__restrict__ qz_out) {
+    __shared__ int s_tk;
+    if (threadIdx.x == 0) s_tk = atomicAdd(ticket, 1);
     __syncthreads();
-    const int base = s_base;
-    for (int c = 0; c < kTilesPerTicket; c++) {
-        const int tk = base + c;
-        if (tk >= ntiles_total) break;
-        sweep_tile<T, KP, UP, HUB>(tk, nlev, lvl_tile, k, perm, flags, ptop, lc_ptr, lc_pos, lc_owner, rpw, yin, F, xout, aggw, done,
-                              epoch_ptr, dep_ptr, dep, ticket, devflags, rdot, dot_part, absmax);
-        __syncthreads();
-    }
+    const int tk = s_tk;
+    if (tk >= ntiles_total) return;
+    sweep_tile<T, KP, UP, HUB, GRAM>(tk, nlev, lvl_tile, k, perm, flags, ptop, lc_ptr, lc_pos, lc_owner, rpw, yin, F,
+                                     xout, aggw, done, epoch_ptr, dep_ptr, dep, ticket, devflags, rdot, dot_part,
+                                     absmax, ntiles_total, qz_q, qz_part, qz_cnt, qz_out);
 }
 
 // start of a solve: reset the sweep tickets and advance the device-side epoch by
@@ -931,11 +947,14 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
 
 template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
-                unsigned long long *absmax, hipStream_t s) {
+                unsigned long long *absmax, hipStream_t s, const T *qz_q, double *qz_part, int *qz_cnt,
+                double *qz_out) {
     const int nt = (int)t.ntiles_used;
-    const int nblk = (nt + kTilesPerTicket - 1) / kTilesPerTicket;
     const double vbytes = 2.0 * d.n * d.k * sizeof(T);
     hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(64), 0, s, t.tickets, t.epoch_dev);
+#define SWEEP_ARGS(TK, DP, DEP, RD, DOT, AM, QQ, QP, QC, QO)                                                    \
+    nt, t.nlev, t.lvl_tile, d.k, t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x,        \
+        v.aggw, t.done, t.epoch_dev, DP, DEP, TK, t.devflags, RD, DOT, AM, QQ, QP, QC, QO
     KP_DISPATCH(d.kp, {
         {
             // y in, subtree sums out; per node: flags, perm, light-child pointers
@@ -943,22 +962,35 @@ void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *r
             // trees with nodes of many light children (hubs) take the variant that sums
             // them in parallel rounds; others keep the lighter kernel
             if (t.max_lc > 2 + kHubPerNode)
-                hipLaunchKernelGGL((k_sweep<T, KP, true, true>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
-                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
-                               (double *)nullptr, (unsigned long long *)nullptr);
+                hipLaunchKernelGGL((k_sweep<T, KP, true, true, false>), dim3(nt), dim3(kSolveThreads), 0, s,
+                                   SWEEP_ARGS(t.tickets, t.dep_up_ptr, t.dep_up, (const T *)nullptr, (double *)nullptr,
+                                              (unsigned long long *)nullptr, (const T *)nullptr, (double *)nullptr,
+                                              (int *)nullptr, (double *)nullptr));
             else
-                hipLaunchKernelGGL((k_sweep<T, KP, true, false>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
-                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_up_ptr, t.dep_up, t.tickets, t.devflags, (const T *)nullptr,
-                               (double *)nullptr, (unsigned long long *)nullptr);
+                hipLaunchKernelGGL((k_sweep<T, KP, true, false, false>), dim3(nt), dim3(kSolveThreads), 0, s,
+                                   SWEEP_ARGS(t.tickets, t.dep_up_ptr, t.dep_up, (const T *)nullptr, (double *)nullptr,
+                                              (unsigned long long *)nullptr, (const T *)nullptr, (double *)nullptr,
+                                              (int *)nullptr, (double *)nullptr));
         }
         {
-            // subtree sums in, potentials out; per node: flags, perm, path top, 1/w
-            ProfScope ps(PK_TREE_DOWN, vbytes + (9.0 + sizeof(T)) * d.n, s);
-            hipLaunchKernelGGL((k_sweep<T, KP, false, false>), dim3(nblk), dim3(kSolveThreads), 0, s, nt, t.nlev, t.lvl_tile, d.k,
-                               t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x, v.aggw, t.done, t.epoch_dev, t.dep_dn_ptr, t.dep_dn, t.tickets + 1, t.devflags, rdot, dot_part,
-                               absmax);
+            // subtree sums in, potentials out; per node: flags, perm, path top, 1/w;
+            // with the fused Gram also the rows of Q
+            const bool gram = UseMF<T, KP>::value && qz_q != nullptr;
+            ProfScope ps(PK_TREE_DOWN, vbytes + (9.0 + sizeof(T)) * d.n + (gram ? (double)d.n * d.k * sizeof(T) : 0.0),
+                         s);
+            if (gram)
+                hipLaunchKernelGGL((k_sweep<T, KP, false, false, UseMF<T, KP>::value>), dim3(nt), dim3(kSolveThreads),
+                                   0, s,
+                                   SWEEP_ARGS(t.tickets + 1, t.dep_dn_ptr, t.dep_dn, rdot, dot_part, absmax, qz_q,
+                                              qz_part, qz_cnt, qz_out));
+            else
+                hipLaunchKernelGGL((k_sweep<T, KP, false, false, false>), dim3(nt), dim3(kSolveThreads), 0, s,
+                                   SWEEP_ARGS(t.tickets + 1, t.dep_dn_ptr, t.dep_dn, rdot, dot_part, absmax,
+                                              (const T *)nullptr, (double *)nullptr, (int *)nullptr,
+                                              (double *)nullptr));
         }
     });
+#undef SWEEP_ARGS
     GR_CHECK_LAUNCH();
 }
 
@@ -1090,7 +1122,7 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
                                int,                                                                              \
                                const unsigned long long *, double *, hipStream_t);                               \
     template void tree_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const T *, double *,            \
-                                unsigned long long *, hipStream_t);                                              \
+                                unsigned long long *, hipStream_t, const T *, double *, int *, double *);        \
     template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, bool, hipStream_t);            \
     template SolveInfo pcg_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const grass_opts &,         \
                                     hipStream_t);                                                                \
