@@ -302,6 +302,12 @@ __global__ __launch_bounds__(NT) void k_bgram(long long n, int k, const T *__res
     if (tail_reduce(tl.part, gridDim.x, NG * KK, tl.cnt, s_w)) tail_finish<KP>(s_w, NG * KK, k, tl.op, tl.vec);
 }
 
+// Workgroups of 1024 threads: at the kernel's occupancy (16 waves per CU) one per CU,
+// so there are few k x k partials (a pair per CU) and the reduction at the end of
+// the launch is two levels of two dependent rounds (256-thread workgroups made it
+// three levels of eight).
+constexpr int kLapGramThreads = 1024;
+
 // Q = L_P P with the Gram matrices P'Q and P'R formed on the fly: a lane group
 // holds one row of P and of Q (KP lanes), which is the operand layout of the FP32
 // MFMA outer products, so each tile adds its rows to the two accumulators before
@@ -309,14 +315,14 @@ __global__ __launch_bounds__(NT) void k_bgram(long long n, int k, const T *__res
 // partials. One pass over P, Q and R instead of a product pass
 // and a three-operand Gram pass.
 template <int KP, int E>
-__global__ __launch_bounds__(kThreads) void k_lap_gram(long long n, int k, const int *__restrict__ rowptr,
+__global__ __launch_bounds__(kLapGramThreads) void k_lap_gram(long long n, int k, const int *__restrict__ rowptr,
                                                        const int *__restrict__ col, const float *__restrict__ val,
                                                        const float *__restrict__ ltail,
                                                        const int *__restrict__ ecol, const float *__restrict__ eval,
                                                        const int *__restrict__ edeg, const float *__restrict__ P,
                                                        float *__restrict__ Q, int root, const float *__restrict__ R,
                                                        Tail<float> tl) {
-    constexpr int G = kThreads / KP, NIT = LapShape<E>::NIT, RPB = G * NIT;
+    constexpr int NT = kLapGramThreads, G = NT / KP, NIT = LapShape<E>::NIT, RPB = G * NIT;
     constexpr int KK = KP * KP;
     __shared__ double s_w[2 * KK];
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;
@@ -334,20 +340,20 @@ __global__ __launch_bounds__(kThreads) void k_lap_gram(long long n, int k, const
     // software pipeline: the next tile's neighbour lists are loaded while this
     // tile's second round (issued first) is in flight
     LapCols<E> cur, nxt;
-    if (xs + q < xe) lap_load<KP, E>((xs + q) * RPB, n, ecol, cur);
+    if (xs + q < xe) lap_load<KP, E, NT>((xs + q) * RPB, n, ecol, cur);
     for (long long t = xs + q; t < xe; t += nq) {
         const long long r0 = t * RPB;
         LapFetch<float, E> F;
         float rv[NIT];
-        lap_fetch<float, KP, E>(r0, n, k, eval, edeg, P, cur, F);
+        lap_fetch<float, KP, E, NT>(r0, n, k, eval, edeg, P, cur, F);
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const long long v = r0 + g + it * G;
             rv[it] = R[act && v < n ? v * k + j : 0];
         }
-        if (t + nq < xe) lap_load<KP, E>((t + nq) * RPB, n, ecol, nxt);
+        if (t + nq < xe) lap_load<KP, E, NT>((t + nq) * RPB, n, ecol, nxt);
         float xo[NIT], yo[NIT];
-        lap_rows<float, KP, E>(r0, n, k, rowptr, col, val, ltail, P, Q, root, 1.f, F, xo, yo);
+        lap_rows<float, KP, E, NT>(r0, n, k, rowptr, col, val, ltail, P, Q, root, 1.f, F, xo, yo);
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const bool ok = act && r0 + g + it * G < n;
@@ -722,21 +728,21 @@ static void launch_gram(const Dims &d, const T *A, const T *B, const T *C, const
 template <typename T, int KP>
 static void launch_lap_gram(Topo &t, Vecs<T> &v, const Dims &d, int root, const Tail<T> &tl, hipStream_t s) {
     if constexpr (UseMF<T, KP>::value) {
-        constexpr long long RPB = (kThreads / KP) * LapShape<kEllP>::NIT;
+        constexpr long long RPB = (kLapGramThreads / KP) * LapShape<kEllP>::NIT;
         // one resident wave of blocks (each walks a range of tiles): more would
         // leave a second, partial wave behind
         static const int resident = [] {
             int dev = 0, cus = 0, per = 0;
             if (hipGetDevice(&dev) != hipSuccess ||
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_lap_gram<KP, kEllP>, kThreads, 0) != hipSuccess)
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_lap_gram<KP, kEllP>, kLapGramThreads, 0) != hipSuccess)
                 return kLapGramBlocks;
             return std::max(8, std::min(kLapGramBlocks, cus * per / 8 * 8));
         }();
         const int nb = (int)std::min<long long>(resident, xcd_grid(div_up(d.n, RPB)));
         ProfScope ps(PK_SPMM_P, 4.0 * (d.n + 1) + (double)d.p_nnz * (4 + sizeof(T)) + 3.0 * d.n * d.k * sizeof(T), s);
         lap_long<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, s);
-        hipLaunchKernelGGL((k_lap_gram<KP, kEllP>), dim3(nb), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol, v.pval,
+        hipLaunchKernelGGL((k_lap_gram<KP, kEllP>), dim3(nb), dim3(kLapGramThreads), 0, s, d.n, d.k, t.prow, t.pcol, v.pval,
                            v.ep.tail, v.ep.col, v.ep.val, v.ep.deg, v.p, v.q, root, v.r, tl);
     } else {
         lap_apply<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, v.q, root, nullptr, nullptr, s);

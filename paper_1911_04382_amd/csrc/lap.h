@@ -22,7 +22,7 @@ struct LapShape {
     static constexpr int NIT = E <= 4 ? 4 : 2;  // rows per lane group
 };
 
-// One tile of kThreads / KP lane groups x NIT rows from row r0: a lane group of KP
+// One tile of NT / KP lane groups x NIT rows from row r0 (NT threads per block): a lane group of KP
 // lanes owns one row per step. Two dependent memory rounds: the neighbour lists
 // (lap_load), then everything else at once (lap_fetch: own values, degrees,
 // weights and neighbour rows); lap_rows forms and stores y. Each round issues all
@@ -39,9 +39,9 @@ struct LapFetch {
     int dg[NIT];
 };
 
-template <int KP, int E>
+template <int KP, int E, int NT = kThreads>
 __device__ __forceinline__ void lap_load(long long r0, long long n, const int *__restrict__ ecol, LapCols<E> &L) {
-    constexpr int G = kThreads / KP;
+    constexpr int G = NT / KP;
     const int g = threadIdx.x / KP;
 #pragma unroll
     for (int it = 0; it < LapShape<E>::NIT; it++) {
@@ -52,11 +52,11 @@ __device__ __forceinline__ void lap_load(long long r0, long long n, const int *_
     }
 }
 
-template <typename T, int KP, int E>
+template <typename T, int KP, int E, int NT = kThreads>
 __device__ __forceinline__ void lap_fetch(long long r0, long long n, int k, const T *__restrict__ eval,
                                           const int *__restrict__ edeg, const T *__restrict__ x,
                                           const LapCols<E> &L, LapFetch<T, E> &F) {
-    constexpr int G = kThreads / KP;
+    constexpr int G = NT / KP;
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;
     const bool act = j < k;
 #pragma unroll
@@ -75,13 +75,13 @@ __device__ __forceinline__ void lap_fetch(long long r0, long long n, int k, cons
 
 // Row `root` is grounded (y = 0); y is scaled by sc. xo / yo return this lane's x
 // and y values (0 outside the matrix), for products that also reduce over rows.
-template <typename T, int KP, int E>
+template <typename T, int KP, int E, int NT = kThreads>
 __device__ __forceinline__ void lap_rows(long long r0, long long n, int k, const int *__restrict__ rowptr,
                                          const int *__restrict__ col, const T *__restrict__ val,
                                          const T *__restrict__ ltail, const T *__restrict__ x, T *__restrict__ y,
                                          int root, T sc, const LapFetch<T, E> &F, T (&xo)[LapShape<E>::NIT],
                                          T (&yo)[LapShape<E>::NIT]) {
-    constexpr int G = kThreads / KP;
+    constexpr int G = NT / KP;
     constexpr int NIT = LapShape<E>::NIT;
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;
     const bool act = j < k;
