@@ -58,29 +58,28 @@ __device__ __forceinline__ void tile_range(long long ntile, int &t0, int &t1) {
 // return 0 there and the direction leaves the search block. Only the leading
 // k x k block takes part; everything else is zero.
 enum SmallOp : int { SM_ALPHA = 0, SM_BETA = 1, SM_NORM = 2 };
-enum TailOp : int { TAIL_STORE = 0, TAIL_SAVE = 1, TAIL_CHECK = 2 };
+// ALPHA / NORM: the block holding the reduced Gram runs that small step itself
+enum TailOp : int { TAIL_STORE = 0, TAIL_SAVE = 1, TAIL_CHECK = 2, TAIL_ALPHA = 3, TAIL_NORM = 4 };
 // FP64 slots of Vecs::small, KP*KP doubles each: G^-1, reduced Gram input (two)
 enum : int { S_GINV = 0, S_IN = 2, S_SLOTS = 4 };
 // working-precision slots of Vecs::smallT (KP*KP each)
 enum : int { T_ALPHA = 0, T_NEGALPHA = 1, T_BETA = 2, T_RINV = 3 };
 
-template <typename T, int KP, int OP>
-__global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ sm, T *__restrict__ outT) {
+template <typename T, int KP, int OP, int NT>
+__device__ void small_op(int k, const double *in, double *__restrict__ ginv, T *__restrict__ outT) {
     constexpr int KK = KP * KP;
     const int tid = threadIdx.x;
-    const double *in = sm + S_IN * KK;
-    double *ginv = sm + S_GINV * KK;
     if constexpr (OP == SM_BETA) {
         // Q'Z and G^-1 staged with coalesced loads (read in place for the widest
         // blocks, LDS-bound)
         constexpr bool STAGE = KP <= 32;
         __shared__ double s_in[STAGE ? 2 * KK : 1];
         if (STAGE) {
-            for (int e = tid; e < 2 * KK; e += kThreads) s_in[e] = e < KK ? in[e] : ginv[e - KK];
+            for (int e = tid; e < 2 * KK; e += NT) s_in[e] = e < KK ? in[e] : ginv[e - KK];
             __syncthreads();
         }
         const double *qz = STAGE ? s_in : in, *gi = STAGE ? s_in + KK : ginv;
-        for (int e = tid; e < KK; e += kThreads) {
+        for (int e = tid; e < KK; e += NT) {
             const int r = e / KP, c = e % KP;
             double acc = 0.0;
             if (r < k && c < k)
@@ -94,7 +93,7 @@ __global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ 
     // the pivot row and the pivot column, which their owners publish to LDS
     // (double-buffered, so one barrier per step).
     constexpr int W = OP == SM_ALPHA ? 3 * KP : 2 * KP;  // [G | RHS | I] or [G | I]
-    constexpr int CG = 32, RG = kThreads / CG;
+    constexpr int CG = 32, RG = NT / CG;
     constexpr int RPT = (KP + RG - 1) / RG, CPT = (W + CG - 1) / CG;
     __shared__ double s_prow[2][W];
     __shared__ double s_pcol[2][KP];
@@ -220,6 +219,11 @@ __global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ 
     }
 }
 
+template <typename T, int KP, int OP>
+__global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ sm, T *__restrict__ outT) {
+    small_op<T, KP, OP, kThreads>(k, sm + S_IN * KP * KP, sm + S_GINV * KP * KP, outT);
+}
+
 template <typename T>
 struct Tail {
     double *part;       // level-0 partials (block b at part + b * width), then the level sums
@@ -229,6 +233,8 @@ struct Tail {
     int *count;         // CHECK: number of vectors not yet converged
     double tol2;
     int op;
+    T *outT;            // ALPHA / NORM: the small-matrix outputs
+    double *ginv;       // ALPHA: G^-1 for the later BETA step
 };
 
 // SAVE / STORE of the reduced total (tot in LDS, width doubles)
@@ -365,7 +371,12 @@ __global__ __launch_bounds__(kLapGramThreads) void k_lap_gram(long long n, int k
     double *out = tl.part + (long long)blockIdx.x * 2 * KK;
     gq.flush(s_w, out);
     gr.flush(s_w, out + KK);
-    if (tail_reduce(tl.part, gridDim.x, 2 * KK, tl.cnt, s_w)) tail_finish<KP>(s_w, 2 * KK, k, tl.op, tl.vec);
+    if (tail_reduce(tl.part, gridDim.x, 2 * KK, tl.cnt, s_w)) {
+        if (tl.op == TAIL_ALPHA)
+            small_op<float, KP, SM_ALPHA, NT>(k, s_w, tl.ginv, tl.outT);
+        else
+            tail_finish<KP>(s_w, 2 * KK, k, tl.op, tl.vec);
+    }
 }
 
 // generic R -= Q alpha; per-block squared column norms of R; the last block counts
@@ -657,7 +668,12 @@ __global__ __launch_bounds__(NT) void k_mf_pupdate(long long n, int k, const flo
     }
     constexpr int KK = KP * KP;
     gram.flush(s_w, tl.part + (long long)blockIdx.x * KK);
-    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) tail_finish<KP>(s_w, KK, k, tl.op, tl.vec);
+    if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) {
+        if (tl.op == TAIL_NORM)
+            small_op<float, KP, SM_NORM, NT>(k, s_w, tl.ginv, tl.outT);
+        else
+            tail_finish<KP>(s_w, KK, k, tl.op, tl.vec);
+    }
 }
 
 // Out = (ADD ? C : 0) + In M, one row tile per wave (Out may alias In or C: each
@@ -784,12 +800,17 @@ static void launch_rupdate(const Dims &d, Vecs<T> &v, Tail<T> tl, hipStream_t s)
                            v.smallT + T_ALPHA * KK, v.q, v.r, tl);
     }
 }
-// X += P alpha, P = Z + P beta and rinv of the new P
+// X += P alpha, P = Z + P beta and the Gram of the new P (with MFMA also rinv from
+// it, in the block that completes the Gram)
 template <typename T, int KP>
 static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s) {
     const int KK = KP * KP;
     ProfScope ps(PK_PUPDATE, 5.0 * d.n * d.k * sizeof(T), s);
     Tail<T> tl = save_tail(v, d);
+    if constexpr (UseMF<T, KP>::value) {
+        tl.op = TAIL_NORM;
+        tl.outT = v.smallT;
+    }
     if constexpr (UseMF<T, KP>::value)
         hipLaunchKernelGGL((k_mf_pupdate<KP, 512>), dim3(kMfGramBlocks), dim3(512), 0, s, d.n, d.k,
                            v.smallT + T_ALPHA * KK, v.smallT + T_BETA * KK, v.z, v.p, v.dx, tl);
@@ -849,9 +870,18 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
         it++;
         bool stop = false, restart = false;
         KP_DISPATCH(d.kp, {
-            // Q = L_P P, P'Q and P'R
-            launch_lap_gram<T, KP>(t, v, d, root, tsave, s);
-            launch_small<T, KP, SM_ALPHA>(d, v, s);
+            // Q = L_P P, P'Q and P'R, then alpha (with MFMA in the block that completes
+            // the Grams)
+            if constexpr (UseMF<T, KP>::value) {
+                Tail<T> ta = tsave;
+                ta.op = TAIL_ALPHA;
+                ta.outT = v.smallT;
+                ta.ginv = v.small + (long long)S_GINV * KK;
+                launch_lap_gram<T, KP>(t, v, d, root, ta, s);
+            } else {
+                launch_lap_gram<T, KP>(t, v, d, root, tsave, s);
+                launch_small<T, KP, SM_ALPHA>(d, v, s);
+            }
             launch_rupdate<T, KP>(d, v, tcheck, s);
             GR_CHECK_LAUNCH();
             const bool last = it >= pp.max_it;
@@ -878,7 +908,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
                 }
                 launch_small<T, KP, SM_BETA>(d, v, s);
                 launch_pupdate<T, KP>(d, v, s);
-                launch_small<T, KP, SM_NORM>(d, v, s);
+                if constexpr (!UseMF<T, KP>::value) launch_small<T, KP, SM_NORM>(d, v, s);
                 launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
             }
             GR_CHECK_LAUNCH();
