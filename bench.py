@@ -94,7 +94,7 @@ def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pcg_kernels_c2_mesh100_traffic.md")
-PROFILED_SOURCES = ["embed.hip", "embed.h", "bpcg.hip", "lap.h", "common.h", "state.h", "kern.h"]
+PROFILED_SOURCES = ["embed.hip", "embed.h", "bpcg.hip", "lap.h", "gram.h", "common.h", "state.h", "kern.h"]
 
 
 def measured_traffic(kernel: str, workload: str):
