@@ -108,6 +108,8 @@ def lib():
         L.orc_pcg.restype = i32
         L.orc_sdd_solve.argtypes = [i64, i64, vp, vp, vp, vp, i32, vp, vp, vp, i32, vp, vp, dbl, i32, dbl, vp]
         L.orc_sdd_solve.restype = i32
+        L.orc_low_stretch_tree.argtypes = [i64, i64, vp, vp, vp, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, vp, vp]
+        L.orc_low_stretch_tree.restype = i64
         L.orc_philox4x64_10.argtypes = [vp, vp, vp]
         L.orc_philox4x64_10.restype = None
         L.orc_gauss_vectors.argtypes = [i64, i32, u64, i64, vp]
@@ -313,6 +315,20 @@ def sparsify(g, opts: Opts | None = None, init_mask=None, trace_cap=256, **kw) -
     sd = {f[0]: getattr(summ, f[0]) for f in Summary._fields_}
     trace = [tr[i].as_dict() for i in range(min(summ.passes, trace_cap))]
     return SparsifyResult(rc, mask, scores, sd, trace)
+
+
+def low_stretch_tree(g, seed=0, class_bits=2, max_rounds=0):
+    """Low-stretch spanning tree (AKPW over weight classes with exponential
+    start-time clustering, Sec. III-A; see orc_low_stretch_tree). Returns the
+    tree mask (m, uint8) and the final cluster of every node."""
+    s, d, w = _edges(g)
+    mask = np.zeros(g.m, np.uint8)
+    cluster = np.empty(g.n, np.int64)
+    rc = lib().orc_low_stretch_tree(g.n, g.m, _p(s), _p(d), _p(w), seed, class_bits, max_rounds, _p(mask),
+                                    _p(cluster))
+    if rc < 0:
+        raise ValueError("class_bits must be >= 1")
+    return mask, cluster
 
 
 def tree_stretch(g, tree_mask):

@@ -694,6 +694,146 @@ int orc_sparsify(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, c
 
 /* ===================================================== test utilities (eqs. 6-8) */
 
+/* ======================================== low-stretch spanning tree (Sec. III-A) */
+
+/* The paper builds on a low-stretch spanning tree and cites the star- and
+ * petal-decomposition constructions. Reading: the AKPW construction (Alon, Karp,
+ * Peleg, West 1995) over weight classes, with its clustering step done by
+ * exponential start-time clustering (Miller, Peng, Xu 2013), a parallel
+ * low-diameter decomposition:
+ *  - class of edge e: (X - ilogb(w_e)) / class_bits with X the largest ilogb(w)
+ *    over the edges: class 0 holds the heaviest edges (shortest, length 1/w),
+ *    each class spans a factor 2^class_bits;
+ *  - round j = 0, 1, ...: the current clusters (initially single nodes, each
+ *    named by a member node) with the edges of class <= j joining two different
+ *    clusters, each of unit length. Every cluster u starts at time
+ *    LS_DMAX - d_u with d_u its shift for round j; a cluster's center is the
+ *    cluster u minimising (hop distance to u) + (start time of u), the smaller
+ *    u on ties. It joins through the heaviest edge (weight rounded to FP32)
+ *    from a cluster of that center one hop nearer, the smaller edge id on ties;
+ *    that edge enters the tree. Clusters then merge into their centers.
+ *  - the rounds end when one cluster is left, or when no edge joins two
+ *    clusters once every class is in (a disconnected graph).
+ *  - shift: the 256 output bits of Philox4x64-10 at counter (u, j, LS_DOMAIN, 0)
+ *    and key (seed, 0) as a stream (bit i is bit i % 64 of word i / 64) of 85
+ *    groups of 3 bits; d_u is the index of the first all-zero group, 85 if none.
+ *    So P(d_u >= k) = (7/8)^k: a geometric stand-in for the exponential shift
+ *    of rate 0.134 that is exact integer arithmetic.
+ * The center rule is computed as a breadth-first expansion over time steps
+ * t = 0 .. LS_DMAX: at step t an unclaimed cluster takes the smallest center
+ * among its own id (if it starts at t) and the centers of its neighbours
+ * claimed at step t - 1. That equals the minimising rule above (a neighbour on
+ * a shortest route from any minimising center is claimed at t - 1 by a center
+ * no larger), which tests check against the direct definition. */
+#define LS_DMAX 85
+#define LS_DOMAIN 0x4C535354ull /* "LSST" */
+
+static int ls_shift(uint64_t seed, int64_t u, int64_t round) {
+    uint64_t ctr[4] = {(uint64_t)u, (uint64_t)round, LS_DOMAIN, 0}, key[2] = {seed, 0}, o[4];
+    orc_philox4x64_10(ctr, key, o);
+    for (int g = 0; g < LS_DMAX; g++) {
+        int v = 0;
+        for (int b = 0; b < 3; b++) {
+            int i = 3 * g + b;
+            v |= (int)((o[i / 64] >> (i % 64)) & 1u) << b;
+        }
+        if (v == 0) return g;
+    }
+    return LS_DMAX;
+}
+
+/* Writes mask[e] = 1 for the tree edges, 0 otherwise, and (if not NULL) the final
+ * cluster of every node into cluster[]. max_rounds > 0 stops after that many
+ * rounds (for tests of one round). Returns the number of tree edges, or
+ * ORC_ERR_INVALID for class_bits < 1. */
+int64_t orc_low_stretch_tree(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                             uint64_t seed, int class_bits, int max_rounds, uint8_t *mask, int64_t *cluster) {
+    if (class_bits < 1) return ORC_ERR_INVALID;
+    int *cls = (int *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int));
+    int64_t *cl = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *owner = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *when = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *start = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *bc = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    int64_t *be = (int64_t *)malloc((size_t)n * sizeof(int64_t));
+    float *bw = (float *)malloc((size_t)n * sizeof(float));
+    int X = 0, maxc = 0;
+    for (int64_t e = 0; e < m; e++) {
+        int x = ilogb(w[e]);
+        if (e == 0 || x > X) X = x;
+    }
+    for (int64_t e = 0; e < m; e++) {
+        cls[e] = (X - ilogb(w[e])) / class_bits;
+        if (cls[e] > maxc) maxc = cls[e];
+        mask[e] = 0;
+    }
+    for (int64_t v = 0; v < n; v++) cl[v] = v;
+    int64_t added = 0;
+    for (int64_t j = 0; max_rounds <= 0 || j < max_rounds; j++) {
+        int64_t nclusters = 0, nactive = 0;
+        for (int64_t v = 0; v < n; v++) nclusters += cl[v] == v;
+        for (int64_t e = 0; e < m; e++) nactive += cls[e] <= j && cl[src[e]] != cl[dst[e]];
+        if (nclusters <= 1) break;
+        if (nactive == 0) {
+            if (j >= maxc) break;
+            continue;
+        }
+        for (int64_t u = 0; u < n; u++) {
+            owner[u] = -1;
+            when[u] = -1;
+            start[u] = cl[u] == u ? LS_DMAX - ls_shift(seed, u, j) : -1;
+        }
+        for (int64_t t = 0; t <= LS_DMAX; t++) {
+            for (int64_t u = 0; u < n; u++) {
+                bc[u] = INT64_MAX;
+                be[u] = -1;
+                bw[u] = 0.0f;
+            }
+            /* smallest offered center */
+            for (int64_t e = 0; e < m; e++) {
+                if (cls[e] > j) continue;
+                int64_t a = cl[src[e]], b = cl[dst[e]];
+                if (a == b) continue;
+                for (int dir = 0; dir < 2; dir++) {
+                    int64_t x = dir ? b : a, y = dir ? a : b;
+                    if (t > 0 && when[x] == t - 1 && owner[y] < 0 && owner[x] < bc[y]) bc[y] = owner[x];
+                }
+            }
+            for (int64_t u = 0; u < n; u++)
+                if (cl[u] == u && owner[u] < 0 && start[u] == t && u < bc[u]) bc[u] = u;
+            /* the joining edge: heaviest (FP32) from that center's clusters, smaller id on ties */
+            for (int64_t e = 0; e < m; e++) {
+                if (cls[e] > j) continue;
+                int64_t a = cl[src[e]], b = cl[dst[e]];
+                if (a == b) continue;
+                for (int dir = 0; dir < 2; dir++) {
+                    int64_t x = dir ? b : a, y = dir ? a : b;
+                    if (!(t > 0 && when[x] == t - 1 && owner[y] < 0 && owner[x] == bc[y])) continue;
+                    float fw = (float)w[e];
+                    if (be[y] < 0 || fw > bw[y] || (fw == bw[y] && e < be[y])) {
+                        be[y] = e;
+                        bw[y] = fw;
+                    }
+                }
+            }
+            for (int64_t u = 0; u < n; u++) {
+                if (cl[u] != u || owner[u] >= 0 || bc[u] == INT64_MAX) continue;
+                owner[u] = bc[u];
+                when[u] = t;
+                if (bc[u] != u) {
+                    mask[be[u]] = 1;
+                    added++;
+                }
+            }
+        }
+        for (int64_t v = 0; v < n; v++) cl[v] = owner[cl[v]];
+    }
+    if (cluster)
+        for (int64_t v = 0; v < n; v++) cluster[v] = cl[v];
+    free(cls); free(cl); free(owner); free(when); free(start); free(bc); free(be); free(bw);
+    return added;
+}
+
 /* Stretch of every edge with respect to the tree {e : tree[e] == 1} (eq. 7):
  * st(p,q) = w_pq * sum over the tree path from p to q of 1 / w_f. Tree edges get
  * stretch 1. Returns the total stretch of eq. (6). Quadratic-time path walk. */

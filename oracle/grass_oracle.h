@@ -62,6 +62,8 @@ int64_t orc_filter_select(int64_t n, int64_t m, const int32_t *src, const int32_
 int orc_sparsify(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
                  const orc_opts *o, const uint8_t *init_mask, uint8_t *mask, double *scores, orc_summary *sum,
                  orc_pass_stats *trace, int trace_cap);
+int64_t orc_low_stretch_tree(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
+                             uint64_t seed, int class_bits, int max_rounds, uint8_t *mask, int64_t *cluster);
 double orc_tree_stretch(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w,
                         const uint8_t *tree, double *stretch);
 #endif

@@ -508,3 +508,122 @@ def test_hair_comb_against_sparse_eigensolver():
     st = O.embed(g, comb, k=4, t=1, lambda_steps=400).stats
     assert st["lambda_max"] <= lam * (1 + 1e-9)
     assert st["lambda_max"] == pytest.approx(lam, rel=2e-3)
+
+
+# ------------------------------------------- low-stretch spanning tree (Sec. III-A)
+def _tree_spans(g, mask):
+    if int(np.asarray(mask).sum()) != g.n - 1:
+        return False
+    ncomp, _ = csg.connected_components(adjacency(g, mask), directed=False)
+    return ncomp == 1
+
+
+LSST_GRAPHS = [
+    G.grid2d(12, 9, weights=(G.W_CONST, 1.0, 1.0)),
+    G.mesh3d(5, 4, 3, weights=(G.W_LOGUNIFORM10, -3, 3), seed=4),
+    G.random_connected(60, 150, weights=(G.W_LOGNORMAL, 0.0, 2.0), seed=11),
+    G.ba(80, 3, seed=5),
+    G.complete(9, seed=1),
+]
+
+
+@pytest.mark.parametrize("g", LSST_GRAPHS, ids=lambda g: g.name)
+@pytest.mark.parametrize("class_bits", [1, 2, 5])
+def test_lsst_is_a_spanning_tree(g, class_bits):
+    mask, cl = O.low_stretch_tree(g, seed=3, class_bits=class_bits)
+    assert _tree_spans(g, mask)
+    assert np.all(cl == cl[0])  # one cluster at the end
+
+
+def test_lsst_of_a_tree_is_the_tree():
+    g = G.random_connected(50, 0, seed=9)  # no extra edges: a random tree
+    assert g.m == g.n - 1
+    mask, _ = O.low_stretch_tree(g, seed=1)
+    assert np.all(mask == 1)
+
+
+def _shift(seed, u, j):
+    """The shift of cluster u in round j, read from the generator's output bits."""
+    o = [int(x) for x in O.philox4x64_10([u, j, 0x4C535354, 0], [seed, 0])]
+    bits = [(o[i // 64] >> (i % 64)) & 1 for i in range(256)]
+    for gi in range(85):
+        if bits[3 * gi] | bits[3 * gi + 1] | bits[3 * gi + 2] == 0:
+            return gi
+    return 85
+
+
+def test_lsst_shift_is_geometric():
+    # P(d >= k) = (7/8)^k; mean 7
+    d = np.array([_shift(11, u, 0) for u in range(4000)])
+    assert abs(d.mean() - 7.0) < 0.4
+    for k in (1, 4, 10):
+        assert abs((d >= k).mean() - (7 / 8) ** k) < 0.03
+
+
+def _hops_from(g, u):
+    return csg.shortest_path(adjacency(g) > 0, unweighted=True, directed=False, indices=u)
+
+
+@pytest.mark.parametrize("g", [G.random_connected(40, 60, seed=2), G.ba(60, 2, seed=3), G.grid2d(7, 6, seed=1)],
+                         ids=lambda g: g.name)
+def test_lsst_round_is_min_shifted_distance(g):
+    """One round from single nodes with every edge in class 0 equals the direct
+    definition: center(v) = argmin_u hops(u, v) + (85 - d_u), ties to the smaller
+    u; v joins through the heaviest FP32 edge to a neighbour one hop nearer to
+    its center inside its cluster (smaller id on ties)."""
+    mask, cl = O.low_stretch_tree(g, seed=7, class_bits=64, max_rounds=1)
+    start = np.array([85 - _shift(7, u, 0) for u in range(g.n)], dtype=float)
+    D = np.stack([_hops_from(g, u) for u in range(g.n)])  # D[u, v]
+    key = D + start[:, None]
+    best = key.min(axis=0)
+    center = np.array([np.flatnonzero(key[:, v] == best[v]).min() for v in range(g.n)])
+    assert np.array_equal(cl, center)
+    w32 = g.w.astype(np.float32)
+    want = np.zeros(g.m, np.uint8)
+    for v in range(g.n):
+        c = center[v]
+        if c == v:
+            continue
+        cands = []
+        for e in range(g.m):
+            a, b = int(g.src[e]), int(g.dst[e])
+            if v not in (a, b):
+                continue
+            x = b if a == v else a
+            if center[x] == c and D[c, x] == D[c, v] - 1:
+                cands.append((-float(w32[e]), e))
+        want[min(cands)[1]] = 1
+    assert np.array_equal(mask, want)
+
+
+def test_lsst_lowers_stretch_on_a_uniform_grid():
+    # with equal weights the maximum-weight tree (ties by edge id) is a comb, whose
+    # total stretch grows like n^1.5; the low-stretch tree stays within m log^2 n
+    g = G.grid2d(48, 48, weights=(G.W_CONST, 1.0, 1.0))
+    mask, _ = O.low_stretch_tree(g, seed=1)
+    _, s_ls = O.tree_stretch(g, mask)
+    _, s_mst = O.tree_stretch(g, O.max_spanning_tree(g))
+    assert s_ls < 0.5 * s_mst
+    assert s_ls < g.m * math.log2(g.n) ** 2
+
+
+def test_lsst_classes_follow_binary_exponents():
+    # weights 1, 2, 4, ..., 2^9 on a path: class_bits = 3 puts edges of exponents
+    # 9..7 in class 0, 6..4 in class 1, 3..1 in class 2, 0 in class 3. Each class
+    # is a set of path edges, so every round keeps joining along the path and the
+    # tree is the path itself whatever the classes; with a chord of weight 2^20
+    # the chord (class 0 alone) must be in the tree.
+    n = 11
+    src = np.arange(n - 1, dtype=np.int32)
+    dst = src + 1
+    w = 2.0 ** np.arange(n - 1)
+    path = G.Graph(n, src, dst, w, "path")
+    mask, _ = O.low_stretch_tree(path, seed=2, class_bits=3)
+    assert np.all(mask == 1)
+    s2 = np.r_[src, np.int32(0)]
+    d2 = np.r_[dst, np.int32(5)]
+    order = np.lexsort((d2, s2))
+    chord = G.Graph(n, s2[order], d2[order], np.r_[w, 2.0 ** 20][order], "path_chord")
+    mask, _ = O.low_stretch_tree(chord, seed=2, class_bits=3)
+    assert _tree_spans(chord, mask)
+    assert mask[np.flatnonzero((chord.src == 0) & (chord.dst == 5))[0]] == 1
