@@ -204,6 +204,51 @@ def run_solve(args, grass, torch):
     print(json.dumps(line), flush=True)
 
 
+def run_lsst(args, grass, torch):
+    """Sec. III-A: the sparsifier built on the low-stretch spanning tree against the
+    one built on the maximum-weight tree, at sigma^2 = 100, k = 32, FP32: tree time,
+    the first pass's lambda_max (the tree's spectral distance to G, bounded by its
+    total stretch), passes, added edges and sparsify time. Graphs: the C2 graph and a
+    unit-weight 60^3 mesh (equal weights, where the maximum-weight tree with ties
+    by edge id is a comb)."""
+    import time
+
+    from paper_1911_04382_amd import graphs as G
+
+    ctx = grass.Context(0)
+    out = {}
+    for name, g in (("c2", G.config_c2(100)), ("unit_mesh60", G.mesh3d(60, 60, 60, weights=(G.W_CONST, 1.0, 1.0)))):
+        dg = grass.to_device(g, "cuda:0")
+        rows = {}
+        for kind in ("max_weight", "low_stretch"):
+            grass.grass_spanning_tree(ctx, dg) if kind == "max_weight" else grass.grass_low_stretch_tree(ctx, dg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tree = (grass.grass_spanning_tree(ctx, dg) if kind == "max_weight"
+                    else grass.grass_low_stretch_tree(ctx, dg, seed=0, class_bits=2))
+            torch.cuda.synchronize()
+            t_tree = (time.perf_counter() - t0) * 1e3
+            opts = grass.make_opts(k=32, t=2, sigma2=100.0, precision=32, init_mask=tree)
+            t0 = time.perf_counter()
+            res = grass.grass_sparsify(ctx, dg, opts)
+            torch.cuda.synchronize()
+            t_sp = (time.perf_counter() - t0) * 1e3
+            rows[kind] = {"tree_ms": round(t_tree, 2), "first_lambda_max": res.trace[0]["lambda_max"],
+                          "passes": res.summary["passes"], "added_edges": res.summary["added_edges"],
+                          "kappa": res.summary["kappa"], "status": res.status, "sparsify_ms": round(t_sp, 1),
+                          "pcg_iters": res.summary["pcg_iters"]}
+            log(f"lsst {name} {kind}: {rows[kind]}")
+        out[name] = {"n": g.n, "m": g.m, **rows}
+    line = {"metric": "sparsify time on the low-stretch spanning tree vs the maximum-weight tree (Sec. III-A)",
+            "value": out["c2"]["low_stretch"]["sparsify_ms"], "unit": "ms (C2 graph)", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "C2 graph (100^3 mesh, 10^U(-3,3)) and a unit-weight 60^3 mesh; sigma^2=100, "
+                                   "k=32, t=2; low-stretch tree seed 0, class_bits 2"},
+            "graphs": out}
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def run_partition(args, grass, torch):
     """Sec. V-F on a synthetic 500 x 500 mesh with random weights: sign cut after 5
     inverse power steps with the sparsifier-preconditioned solver at 1e-3 against
@@ -361,6 +406,8 @@ def main():
         return run_solve(args, grass, torch)
     if args.workload == "partition":
         return run_partition(args, grass, torch)
+    if args.workload == "lsst":
+        return run_lsst(args, grass, torch)
 
     g, cfg, desc = workload(args.workload)
     for kv in args.opt:

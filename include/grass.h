@@ -193,6 +193,24 @@ void grass_server_destroy(grass_server *srv);
 grass_status grass_spanning_tree(grass_ctx *ctx, const grass_graph *g, uint8_t *tree_mask, void *workspace,
                                  size_t ws_bytes, void *stream);
 
+/* Low-stretch spanning tree (Sec. III-A builds the sparsifier on a low-stretch
+ * tree; the paper cites star and petal decompositions). This one is the AKPW
+ * construction over binary weight classes (class of e = (max ilogb(w) - ilogb(w_e))
+ * / class_bits, class 0 the heaviest) with exponential start-time clustering in
+ * each round: cluster u starts at 85 - d_u, d_u a geometric shift (P(d >= k) =
+ * (7/8)^k) read from Philox4x64-10 at counter (u, round, 0x4C535354, 0), key
+ * (seed, 0); a cluster joins the center minimising hops + start (smaller id on
+ * ties) through the heaviest FP32 edge from a cluster one hop nearer to it (smaller
+ * edge id on ties). tree_mask: device uint8 [m], 1 for the n-1 tree edges, else 0;
+ * pass it to grass_sparsify as opts->init_mask to build on it. class_bits >= 1.
+ * The tree depends only on the graph, seed and class_bits. Errors:
+ * GRASS_ERR_INVALID (bad graph or class_bits), GRASS_ERR_DISCONNECTED. workspace:
+ * grass_low_stretch_tree_workspace_bytes(n, m) device bytes, or NULL for the
+ * context's own memory. */
+size_t grass_low_stretch_tree_workspace_bytes(int64_t n, int64_t m);
+grass_status grass_low_stretch_tree(grass_ctx *ctx, const grass_graph *g, uint64_t seed, int32_t class_bits,
+                                    uint8_t *tree_mask, void *workspace, size_t ws_bytes, void *stream);
+
 /* One pass of embedding and scoring for a given subgraph P (Sec. III-F, eqs. 28-35,
  * 55, 61): p_mask device uint8 [m] (1 = spanning-tree edge, 2 = added edge, 0 = off;
  * the 1-edges must span G); pass = the Philox counter word of the start vectors.

@@ -137,6 +137,11 @@ def load_library(path: str = LIB_PATH):
     L.grass_sparsify.restype = st
     L.grass_spanning_tree.argtypes = [vp, ctypes.POINTER(grass_graph), vp, vp, ctypes.c_size_t, vp]
     L.grass_spanning_tree.restype = st
+    L.grass_low_stretch_tree_workspace_bytes.argtypes = [i64, i64]
+    L.grass_low_stretch_tree_workspace_bytes.restype = ctypes.c_size_t
+    L.grass_low_stretch_tree.argtypes = [vp, ctypes.POINTER(grass_graph), ctypes.c_uint64, i32, vp, vp, ctypes.c_size_t,
+                                         vp]
+    L.grass_low_stretch_tree.restype = st
     L.grass_embed.argtypes = [vp, ctypes.POINTER(grass_graph), vp, ctypes.POINTER(grass_opts), i32, vp,
                               ctypes.POINTER(grass_pass_stats), vp, ctypes.c_size_t, vp]
     L.grass_embed.restype = st
@@ -444,6 +449,24 @@ def grass_spanning_tree(ctx: Context, g: DeviceGraph, ws=None, stream=None):
     wsp, wsb = _ws_args(ws)
     ctx.check(ctx.lib.grass_spanning_tree(ctx.h, ctypes.byref(gc), ctypes.c_void_p(mask.data_ptr()), wsp, wsb,
                                           _stream_ptr(stream)))
+    return mask
+
+
+def low_stretch_tree_workspace(g: DeviceGraph, device="cuda:0"):
+    """A uint8 device tensor of grass_low_stretch_tree_workspace_bytes()."""
+    torch = _torch()
+    nbytes = load_library().grass_low_stretch_tree_workspace_bytes(g.n, g.m)
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def grass_low_stretch_tree(ctx: Context, g: DeviceGraph, seed=0, class_bits=2, ws=None, stream=None):
+    """Low-stretch spanning tree mask (device uint8 [m]); see include/grass.h."""
+    torch = _torch()
+    mask = torch.empty(g.m, dtype=torch.uint8, device=g.src.device)
+    gc = g.c()
+    wsp, wsb = _ws_args(ws)
+    ctx.check(ctx.lib.grass_low_stretch_tree(ctx.h, ctypes.byref(gc), ctypes.c_uint64(seed), int(class_bits),
+                                             ctypes.c_void_p(mask.data_ptr()), wsp, wsb, _stream_ptr(stream)))
     return mask
 
 

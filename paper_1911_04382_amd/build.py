@@ -12,7 +12,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgrass.so")
-SOURCES = ["prim.hip", "graph.hip", "embed.hip", "bpcg.hip", "select.hip", "api.hip", "serve.hip", "sdd.hip"]
+SOURCES = ["prim.hip", "graph.hip", "embed.hip", "bpcg.hip", "select.hip", "api.hip", "serve.hip", "sdd.hip", "lsst.hip"]
 ARCH = os.environ.get("GRASS_OFFLOAD_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 instructions.

@@ -9,6 +9,7 @@
 #include "embed.h"
 #include "graph.h"
 #include "kern.h"
+#include "lsst.h"
 #include "profiler.h"
 #include "select.h"
 
@@ -524,6 +525,33 @@ grass_status grass_spanning_tree(grass_ctx *ctx, const grass_graph *g, uint8_t *
         S.t.w = g->w;
         validate_graph(S.t, s);
         boruvka(S.t, S.st, tree_mask, s);
+        GR_HIP(hipStreamSynchronize(s));
+        return GRASS_OK;
+    });
+}
+
+size_t grass_low_stretch_tree_workspace_bytes(int64_t n, int64_t m) {
+    if (n < 0 || m < 0) return 0;
+    return lsst_bytes(n, m);
+}
+
+grass_status grass_low_stretch_tree(grass_ctx *ctx, const grass_graph *g, uint64_t seed, int32_t class_bits,
+                                    uint8_t *tree_mask, void *workspace, size_t ws_bytes, void *stream) {
+    return guarded(ctx, [&]() -> grass_status {
+        check_graph(g);
+        require(tree_mask != nullptr, GRASS_ERR_INVALID, "tree_mask is required");
+        require(class_bits >= 1 && class_bits <= 64, GRASS_ERR_INVALID, "class_bits must be in 1..64");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        Arena a = bind_arena(ctx, workspace, ws_bytes, lsst_bytes(g->n, g->m));
+        Topo t;
+        t.n = g->n;
+        t.m = g->m;
+        t.src = g->src;
+        t.dst = g->dst;
+        t.w = g->w;
+        t.devflags = a.take<unsigned>(4);
+        validate_graph(t, s);
+        low_stretch_tree(t, a, seed, class_bits, tree_mask, s);
         GR_HIP(hipStreamSynchronize(s));
         return GRASS_OK;
     });

@@ -23,7 +23,8 @@ def test_header_declares_the_boundary_calls():
                  "grass_sparsify", "grass_spanning_tree", "grass_embed", "grass_select", "grass_start_vectors",
                  "grass_sparsify_batch", "grass_batch_workspace_bytes", "grass_server_create", "grass_server_submit",
                  "grass_solve", "grass_solve_workspace_bytes", "grass_partition",
-                 "grass_partition_workspace_bytes"):
+                 "grass_partition_workspace_bytes", "grass_low_stretch_tree",
+                 "grass_low_stretch_tree_workspace_bytes"):
         assert name in declared
 
 
@@ -47,6 +48,13 @@ def test_workspace_bytes_monotone_and_rejects_bad_sizes():
     assert lib.grass_workspace_bytes(1, 0, ctypes.byref(o)) == 0
     o.k = 65
     assert lib.grass_workspace_bytes(1000, 3000, ctypes.byref(o)) == 0
+
+
+def test_low_stretch_tree_workspace_bytes():
+    lib = grass.load_library()
+    small = lib.grass_low_stretch_tree_workspace_bytes(1000, 3000)
+    assert 1000 * 28 + 3000 * 4 <= small < lib.grass_low_stretch_tree_workspace_bytes(100000, 300000)
+    assert lib.grass_low_stretch_tree_workspace_bytes(-1, 3) == 0
 
 
 def test_null_context_is_rejected():
