@@ -39,11 +39,22 @@ inline int blocks_for(long long n) { return (int)std::max<long long>(1, std::min
 #define LS_STRIDE(i, n) \
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
 
+// one atomic per wave: the wave's maximum / sum first
+__device__ __forceinline__ int wave_max(int x) {
+    for (int o = 32; o >= 1; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ __forceinline__ int wave_sum(int x) {
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
 // counters: [0] largest ilogb(w), [1] largest class, [2] clusters, [3] active edges
 __global__ void k_ls_exp(long long m, const double *__restrict__ w, int *__restrict__ cnt) {
     int mx = INT_MIN;
     LS_STRIDE(e, m) mx = max(mx, ilogb(w[e]));
-    if (mx != INT_MIN) atomicMax(&cnt[0], mx);
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0 && mx != INT_MIN) atomicMax(&cnt[0], mx);
 }
 
 __global__ void k_ls_class(long long m, const double *__restrict__ w, int bits, int *__restrict__ cls,
@@ -55,7 +66,8 @@ __global__ void k_ls_class(long long m, const double *__restrict__ w, int bits, 
         cls[e] = c;
         mx = max(mx, c);
     }
-    atomicMax(&cnt[1], mx);
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) atomicMax(&cnt[1], mx);
 }
 
 __global__ void k_ls_iota(long long n, int *__restrict__ cl) {
@@ -67,8 +79,12 @@ __global__ void k_ls_count(long long n, long long m, int j, const int *__restric
     int nc = 0, na = 0;
     LS_STRIDE(v, n) nc += cl[v] == (int)v;
     LS_STRIDE(e, m) na += cls[e] <= j && cl[src[e]] != cl[dst[e]];
-    if (nc) atomicAdd(&cnt[2], nc);
-    if (na) atomicAdd(&cnt[3], na);
+    nc = wave_sum(nc);
+    na = wave_sum(na);
+    if ((threadIdx.x & 63) == 0) {
+        if (nc) atomicAdd(&cnt[2], nc);
+        if (na) atomicAdd(&cnt[3], na);
+    }
 }
 
 // start times of the round's clusters; clears the claim state
