@@ -144,14 +144,20 @@ def run_batch(args, grass, torch):
     torch.cuda.synchronize()
     log(f"C4: {len(gs)} graphs, {sum(g.n for g in gs)} nodes, {sum(g.m for g in gs)} edges")
     t0 = time.perf_counter()
-    plain = [grass.grass_sparsify(ctx, dg, opts) for dg in dgs]
+    plain = []
+    for i, dg in enumerate(dgs):
+        plain.append(grass.grass_sparsify(ctx, dg, opts))  # returns when the graph is done
+        if (i + 1) % 8 == 0:
+            log(f"plain path: {i + 1}/{len(dgs)} graphs at {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     ws = grass.batch_workspace(dgs, opts, args.workers)
     t0 = time.perf_counter()
+    log(f"batch path: {len(dgs)} graphs, {args.workers} workers ...")
     rc, out = grass.grass_sparsify_batch(ctx, dgs, opts, workers=args.workers, ws=ws)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
+    log(f"batch path: done in {t_batch:.1f} s")
     same = all(torch.equal(a.mask, b.mask) and torch.equal(a.scores, b.scores) for a, b in zip(out, plain))
     scored = sum(r.summary["scored_edges"] for r in out)
     line = {"metric": "off-tree edges scored/sec, batch of independent graphs", "value": scored / t_batch,
