@@ -188,7 +188,11 @@ def run_solve(args, grass, torch):
     gen = torch.Generator(device="cpu").manual_seed(7)
     b = torch.randn(g.n, 16, generator=gen, dtype=torch.float32)
     b = (b - b.mean(0)).to("cuda:0")
-    sopts = grass.make_opts(k=16, precision=32, pcg_rtol=1e-1)  # inner L_P solves inside flexible CG
+    # each application of the sparsifier: 16 block-PCG iterations on L_P, no FP64
+    # restart (flexible CG absorbs the inexact, varying preconditioner); measured
+    # against inner solves to a tolerance: 1e-1 took 3.3 s, 5e-1 2.1 s, a fixed 8
+    # iterations 1.12 s, 16 1.07 s, 32 1.50 s
+    sopts = grass.make_opts(k=16, precision=32, pcg_rtol=1e-3, pcg_max_iters=16, pcg_max_outer=1)
     out = {}
     for label, mask in (("sparsifier", res.mask), ("tree", None)):
         ws = grass.solve_workspace(dg, sopts)
@@ -203,7 +207,8 @@ def run_solve(args, grass, torch):
             "value": out["sparsifier"]["ms"], "unit": "ms (16 right-hand sides)", "n_gpus": 1,
             "higher_is_better": False, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "C2 graph (100^3 mesh, 10^U(-3,3)), sparsifier from grass_sparsify at sigma^2=100, "
-                                   "16 seeded Gaussian right-hand sides (mean removed), inner L_P solves to 1e-1"},
+                                   "16 seeded Gaussian right-hand sides (mean removed), each preconditioner application "
+                                   "16 block-PCG iterations on L_P"},
             "sparsifier": out["sparsifier"], "tree": out["tree"],
             "iteration_ratio_tree_over_sparsifier": out["tree"]["iters"] / max(1, out["sparsifier"]["iters"])}
     ctx.close()
