@@ -119,6 +119,8 @@ def test_embed_tree_pass(ctx, case):
 PCG_CASES = [
     ("grid_fp64", lambda: G.grid2d(40, 40, seed=3), 8, 64),
     ("mesh_fp32", lambda: G.mesh3d(16, 15, 14, weights=(G.W_LOGUNIFORM10, -3, 3), seed=4), 16, 32),
+    # k = 32: the 32 x 32 x 2 MFMA product, sweep and update kernels the benchmark runs
+    ("mesh_fp32_k32", lambda: G.mesh3d(18, 16, 15, weights=(G.W_LOGUNIFORM10, -3, 3), seed=6), 32, 32),
     # hubs: L_P rows past the long-row bound (their tails summed by a workgroup each)
     ("ba_hubs_fp32", lambda: G.ba(12000, seed=5), 16, 32),
 ]
@@ -275,6 +277,39 @@ def test_full_size_tree_pass(ctx, case):
     assert rel <= 1e-3
     assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
     assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
+
+
+def test_full_size_pcg_pass_c2(ctx):
+    """A densified pass of the benchmark workload at its full size (C2, k = 32, FP32:
+    the fused MFMA block-PCG kernels) against the library's FP64 path (generic
+    kernels, parity-tested against the oracle above) on the same P; the oracle's
+    own PCG at this size would take minutes. lambda_min is checked against the
+    exact degree ratio computed here, and two runs must agree bit for bit."""
+    g = G.config_c2(100)
+    say("full-size PCG pass: C2", g.n, g.m)
+    dg = grass.to_device(g, DEV)
+    tm = grass.grass_spanning_tree(ctx, dg)
+    o32 = grass.make_opts(k=32, t=2, precision=32, seed=0)
+    heat0, st0 = grass.grass_embed(ctx, dg, tm, o32, pass_=0)
+    _, sel = grass.grass_select(ctx, dg, tm, o32, heat0, st0["lambda_max"], st0["lambda_min"])
+    P = tm.cpu().numpy()
+    assert (P == 2).sum() > 1000  # edges were added: the pass below runs the block PCG
+    heat, st = grass.grass_embed(ctx, dg, tm, o32, pass_=1)
+    heat2, _ = grass.grass_embed(ctx, dg, tm, o32, pass_=1)
+    assert torch.equal(heat, heat2)
+    h64, st64 = grass.grass_embed(ctx, dg, tm, grass.make_opts(k=32, t=2, precision=64, seed=0, pcg_rtol=1e-10),
+                                  pass_=1)
+    off = P == 0
+    err, s, r = _norm_err(heat.cpu().numpy().astype(np.float64), h64.cpu().numpy(), off)
+    say(f"  pcg iters {st['pcg_iters']} (FP64 {st64['pcg_iters']}), resid64 {st['pcg_resid64']:.2e}, "
+        f"max score err {err:.3e}, lambda_max {st['lambda_max']:.6g} vs {st64['lambda_max']:.6g}")
+    assert st["pcg_resid64"] <= 1e-6
+    assert err <= 1e-4
+    assert st["lambda_max"] == pytest.approx(st64["lambda_max"], rel=1e-4)
+    inP = P != 0
+    degG = np.bincount(np.r_[g.src, g.dst], weights=np.r_[g.w, g.w], minlength=g.n)
+    degP = np.bincount(np.r_[g.src[inP], g.dst[inP]], weights=np.r_[g.w[inP], g.w[inP]], minlength=g.n)
+    assert st["lambda_min"] == pytest.approx((degG / degP).min(), rel=1e-12)
 
 
 def test_pcg_pass_medium_mesh(ctx):
