@@ -49,6 +49,24 @@ struct BlockGram {
     __device__ void flush(double *s, double *__restrict__ out) {
         const int G = blockDim.x / KP;
         const int g = threadIdx.x / KP, j = threadIdx.x % KP;
+        if constexpr (KP <= 8) {
+            // narrow blocks have many lane groups (256 at k = 1): every group stores
+            // its accumulators at once and each entry is summed over the groups in
+            // group order, the order of the fold below, so the bits are the same
+            __shared__ double s_all[kThreads * KP];
+            if (blockDim.x <= kThreads) {
+                __syncthreads();
+                for (int i = 0; i < KP; i++) s_all[(g * KP + i) * KP + j] = (double)acc[i];
+                __syncthreads();
+                for (int e = threadIdx.x; e < KP * KP; e += blockDim.x) {
+                    double t = 0.0;
+                    for (int q = 0; q < G; q++) t += s_all[q * KP * KP + e];
+                    st_agent(&out[e], t);
+                }
+                __syncthreads();
+                return;
+            }
+        }
         __syncthreads();
         for (int gg = 0; gg < G; gg++) {
             if (g == gg)
