@@ -732,6 +732,12 @@ long long bpcg_part_doubles(const Dims &d) {
 }
 long long bpcg_counters(const Dims &d) { return tail_items(tail_grid_max(d)) + 64; }
 
+// generic Gram passes: one workgroup per row tile up to gram_blocks (a multiple of
+// 8, as the XCD mapping needs), so a small graph reduces few partials
+template <int KP>
+static int gram_grid(long long n) {
+    return std::min(gram_blocks(KP), xcd_grid(div_up(n, (long long)BShape<KP>::RPT)));
+}
 // Gram launch shape: with MFMA one 1024-thread workgroup per CU (256 partials, two
 // reduction levels), else 256-thread workgroups
 constexpr int kMfGramBlocks = 256;
@@ -740,7 +746,7 @@ static void launch_gram(const Dims &d, const T *A, const T *B, const T *C, const
     if constexpr (UseMF<T, KP>::value)
         hipLaunchKernelGGL((k_bgram<T, KP, NG, 1024>), dim3(kMfGramBlocks), dim3(1024), 0, s, d.n, d.k, A, B, C, tl);
     else
-        hipLaunchKernelGGL((k_bgram<T, KP, NG, kThreads>), dim3(gram_blocks(KP)), dim3(kThreads), 0, s, d.n, d.k, A,
+        hipLaunchKernelGGL((k_bgram<T, KP, NG, kThreads>), dim3(gram_grid<KP>(d.n)), dim3(kThreads), 0, s, d.n, d.k, A,
                            B, C, tl);
 }
 // Q = L_P P, then P'Q and P'R: fused for FP32 blocks of 16 or 32 vectors, else a
@@ -819,7 +825,7 @@ static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s) {
         hipLaunchKernelGGL((k_mf_pupdate<KP, 512>), dim3(kMfGramBlocks), dim3(512), 0, s, d.n, d.k,
                            v.smallT + T_ALPHA * KK, v.smallT + T_BETA * KK, v.z, v.p, v.dx, tl);
     else
-        hipLaunchKernelGGL((k_pupdate<T, KP>), dim3(gram_blocks(KP)), dim3(kThreads), 0, s, d.n, d.k,
+        hipLaunchKernelGGL((k_pupdate<T, KP>), dim3(gram_grid<KP>(d.n)), dim3(kThreads), 0, s, d.n, d.k,
                            v.smallT + T_ALPHA * KK, v.smallT + T_BETA * KK, v.z, v.p, v.dx, tl);
 }
 // Out = (ADD ? C : 0) + In M
