@@ -908,15 +908,17 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
             }
             if (!stop && !restart) {
                 if constexpr (UseMF<T, KP>::value) {
-                    // Z = L_T^+ R with Q'Z formed by the down sweep's tiles
+                    // Z = L_T^+ R with Q'Z and beta formed by the down sweep's tiles
                     tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s, v.q, tsave.part, tsave.cnt,
-                                  tsave.vec);
+                                  nullptr, v.small + (long long)S_GINV * KK, v.smallT + T_BETA * KK);
                 } else {
                     tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
-                    ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
-                    launch_gram<T, KP, 1>(d, v.q, v.z, nullptr, tsave, s);
+                    {
+                        ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
+                        launch_gram<T, KP, 1>(d, v.q, v.z, nullptr, tsave, s);
+                    }
+                    launch_small<T, KP, SM_BETA>(d, v, s);
                 }
-                launch_small<T, KP, SM_BETA>(d, v, s);
                 launch_pupdate<T, KP>(d, v, s);
                 if constexpr (!UseMF<T, KP>::value) launch_small<T, KP, SM_NORM>(d, v, s);
                 launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);

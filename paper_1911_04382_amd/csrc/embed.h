@@ -37,11 +37,13 @@ void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, co
 // per-tile partials of rdot.x, max|x| (u64 slot bits of a double).
 // With qz_q (FP32 at k = 16 or 32 only): the down sweep's tiles also form the Gram
 // Q'x (qz_q n x k) from per-tile FP64 partials in qz_part (counters qz_cnt), and the
-// last tile stores the k x k total (row-major, ld kp) at qz_out.
+// last tile stores the k x k total (row-major, ld kp) at qz_out or, with beta_out,
+// stores beta = -G^-1 Q'x there instead (G^-1 at beta_ginv, both k x k, ld kp).
 template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s, const T *qz_q = nullptr, double *qz_part = nullptr,
-                int *qz_cnt = nullptr, double *qz_out = nullptr);
+                int *qz_cnt = nullptr, double *qz_out = nullptr, const double *beta_ginv = nullptr,
+                T *beta_out = nullptr);
 
 // L_P solve: block PCG in working precision with the tree preconditioner, refined
 // in FP64: whenever every vector's recursive residual has fallen by

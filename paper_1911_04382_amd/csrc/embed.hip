@@ -202,7 +202,8 @@ __device__ __forceinline__ void sweep_tile(
     const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr, const int *__restrict__ dep,
     int *__restrict__ ticket, unsigned *__restrict__ devflags, const T *__restrict__ rdot,
     double *__restrict__ dot_part, unsigned long long *__restrict__ absmax, int ntiles_total,
-    const T *__restrict__ qz_q, double *__restrict__ qz_part, int *__restrict__ qz_cnt, double *__restrict__ qz_out) {
+    const T *__restrict__ qz_q, double *__restrict__ qz_part, int *__restrict__ qz_cnt, double *__restrict__ qz_out,
+    const double *__restrict__ beta_ginv, T *__restrict__ beta_out) {
     constexpr int RUNS = kSolveThreads / KP;
     constexpr int NPR = solve_npr(KP);
     constexpr int TN = RUNS * NPR;
@@ -565,8 +566,21 @@ __device__ __forceinline__ void sweep_tile(
 #pragma unroll
         for (int q = 0; q < NPR; q++) gq.add(qv[q], vals[q]);
         gq.flush(s_gw, qz_part + (long long)tk * KK);
-        if (tail_reduce(qz_part, ntiles_total, KK, qz_cnt, s_gw, tk))
-            for (int e = tid; e < KK; e += kSolveThreads) qz_out[e] = s_gw[e];
+        if (tail_reduce(qz_part, ntiles_total, KK, qz_cnt, s_gw, tk)) {
+            if (beta_out) {
+                // the k x k step that follows this Gram, by the block that holds the
+                // total: beta = -G^-1 Q'x (G^-1 saved by the alpha step)
+                for (int e = tid; e < KK; e += kSolveThreads) {
+                    const int rr = e / KP, cc = e % KP;
+                    double acc = 0.0;
+                    if (rr < k && cc < k)
+                        for (int p = 0; p < k; p++) acc -= beta_ginv[rr * KP + p] * s_gw[p * KP + cc];
+                    beta_out[e] = (T)acc;
+                }
+            } else {
+                for (int e = tid; e < KK; e += kSolveThreads) qz_out[e] = s_gw[e];
+            }
+        }
     }
 
     if (!UP) {
@@ -604,7 +618,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_sweep(
     unsigned *__restrict__ done, const unsigned *__restrict__ epoch_ptr, const int *__restrict__ dep_ptr,
     const int *__restrict__ dep, int *__restrict__ ticket, unsigned *__restrict__ devflags,
     const T *__restrict__ rdot, double *__restrict__ dot_part, unsigned long long *__restrict__ absmax,
-    const T *__restrict__ qz_q, double *__restrict__ qz_part, int *__restrict__ qz_cnt, double *__restrict__ qz_out) {
+    const T *__restrict__ qz_q, double *__restrict__ qz_part, int *__restrict__ qz_cnt, double *__restrict__ qz_out,
+    const double *__restrict__ beta_ginv, T *__restrict__ beta_out) {
     __shared__ int s_tk;
     if (threadIdx.x == 0) s_tk = atomicAdd(ticket, 1);
     __syncthreads();
@@ -612,7 +627,7 @@ __global__ __launch_bounds__(kSolveThreads) void k_sweep(
     if (tk >= ntiles_total) return;
     sweep_tile<T, KP, UP, HUB, GRAM>(tk, nlev, lvl_tile, k, perm, flags, ptop, lc_ptr, lc_pos, lc_owner, rpw, yin, F,
                                      xout, aggw, done, epoch_ptr, dep_ptr, dep, ticket, devflags, rdot, dot_part,
-                                     absmax, ntiles_total, qz_q, qz_part, qz_cnt, qz_out);
+                                     absmax, ntiles_total, qz_q, qz_part, qz_cnt, qz_out, beta_ginv, beta_out);
 }
 
 // start of a solve: reset the sweep tickets and advance the device-side epoch by
@@ -948,13 +963,13 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
 template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s, const T *qz_q, double *qz_part, int *qz_cnt,
-                double *qz_out) {
+                double *qz_out, const double *beta_ginv, T *beta_out) {
     const int nt = (int)t.ntiles_used;
     const double vbytes = 2.0 * d.n * d.k * sizeof(T);
     hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(64), 0, s, t.tickets, t.epoch_dev);
-#define SWEEP_ARGS(TK, DP, DEP, RD, DOT, AM, QQ, QP, QC, QO)                                                    \
+#define SWEEP_ARGS(TK, DP, DEP, RD, DOT, AM, QQ, QP, QC, QO, BG, BO)                                            \
     nt, t.nlev, t.lvl_tile, d.k, t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x,        \
-        v.aggw, t.done, t.epoch_dev, DP, DEP, TK, t.devflags, RD, DOT, AM, QQ, QP, QC, QO
+        v.aggw, t.done, t.epoch_dev, DP, DEP, TK, t.devflags, RD, DOT, AM, QQ, QP, QC, QO, BG, BO
     KP_DISPATCH(d.kp, {
         {
             // y in, subtree sums out; per node: flags, perm, light-child pointers
@@ -965,12 +980,14 @@ void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *r
                 hipLaunchKernelGGL((k_sweep<T, KP, true, true, false>), dim3(nt), dim3(kSolveThreads), 0, s,
                                    SWEEP_ARGS(t.tickets, t.dep_up_ptr, t.dep_up, (const T *)nullptr, (double *)nullptr,
                                               (unsigned long long *)nullptr, (const T *)nullptr, (double *)nullptr,
-                                              (int *)nullptr, (double *)nullptr));
+                                              (int *)nullptr, (double *)nullptr, (const double *)nullptr,
+                                              (T *)nullptr));
             else
                 hipLaunchKernelGGL((k_sweep<T, KP, true, false, false>), dim3(nt), dim3(kSolveThreads), 0, s,
                                    SWEEP_ARGS(t.tickets, t.dep_up_ptr, t.dep_up, (const T *)nullptr, (double *)nullptr,
                                               (unsigned long long *)nullptr, (const T *)nullptr, (double *)nullptr,
-                                              (int *)nullptr, (double *)nullptr));
+                                              (int *)nullptr, (double *)nullptr, (const double *)nullptr,
+                                              (T *)nullptr));
         }
         {
             // subtree sums in, potentials out; per node: flags, perm, path top, 1/w;
@@ -982,12 +999,12 @@ void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *r
                 hipLaunchKernelGGL((k_sweep<T, KP, false, false, UseMF<T, KP>::value>), dim3(nt), dim3(kSolveThreads),
                                    0, s,
                                    SWEEP_ARGS(t.tickets + 1, t.dep_dn_ptr, t.dep_dn, rdot, dot_part, absmax, qz_q,
-                                              qz_part, qz_cnt, qz_out));
+                                              qz_part, qz_cnt, qz_out, beta_ginv, beta_out));
             else
                 hipLaunchKernelGGL((k_sweep<T, KP, false, false, false>), dim3(nt), dim3(kSolveThreads), 0, s,
                                    SWEEP_ARGS(t.tickets + 1, t.dep_dn_ptr, t.dep_dn, rdot, dot_part, absmax,
                                               (const T *)nullptr, (double *)nullptr, (int *)nullptr,
-                                              (double *)nullptr));
+                                              (double *)nullptr, (const double *)nullptr, (T *)nullptr));
         }
     });
 #undef SWEEP_ARGS
@@ -1122,7 +1139,8 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
                                int,                                                                              \
                                const unsigned long long *, double *, hipStream_t);                               \
     template void tree_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const T *, double *,            \
-                                unsigned long long *, hipStream_t, const T *, double *, int *, double *);        \
+                                unsigned long long *, hipStream_t, const T *, double *, int *, double *,         \
+                                const double *, T *);                                                            \
     template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, bool, hipStream_t);            \
     template SolveInfo pcg_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const grass_opts &,         \
                                     hipStream_t);                                                                \
