@@ -26,9 +26,12 @@
  *  - similarity check: topological greedy (Sec. IV-D step 6 gives no measure);
  *  - per-pass edge budget floor(budget_frac * n) ("a small portion", Sec. III-I
  *    step 5 and Sec. IV-D).
- * Parity unpinned by the paper: the similarity check, the per-pass budget, the
- * PCG tolerance and the lambda_max step count (they are fixed only by the
- * readings above).
+ * The paper fixes no values for the similarity check, the per-pass budget, the
+ * PCG tolerance or the lambda_max step count; the tests pin this code to the
+ * readings above instead: the greedy to a hand-worked example and to its
+ * defining property (Sec. IV-D step 6), the lambda_max estimate to the largest
+ * dense Rayleigh quotient over the vectors (Sec. IV-C.1), the lambda_min
+ * estimate to the smallest dense degree ratio (eq. 61).
  */
 #include <math.h>
 #include <stdint.h>

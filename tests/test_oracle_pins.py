@@ -627,3 +627,140 @@ def test_lsst_classes_follow_binary_exponents():
     mask, _ = O.low_stretch_tree(chord, seed=2, class_bits=3)
     assert _tree_spans(chord, mask)
     assert mask[np.flatnonzero((chord.src == 0) & (chord.dst == 5))[0]] == 1
+
+
+# ------------------------- the estimators and the greedy, each pinned to its definition
+def _dense_power_vectors(g, inP, k, t, seed, pass_):
+    """h_t = (L_P^+ L_G)^t h_0 with dense pseudo-inverses (eq. 29); h_0 from eq. (28)."""
+    h = O.gauss_vectors(g.n, k, seed, pass_)
+    LG = dense_laplacian(g)
+    LPp = np.linalg.pinv(dense_laplacian(g, inP))
+    for _ in range(t):
+        h = LPp @ (LG @ h)
+        h /= np.abs(h).max(axis=0)  # the quotient below is scale-invariant per vector
+    return h
+
+
+def _subgraphs(g):
+    tmask = O.max_spanning_tree(g)
+    P = tmask.copy()
+    off = np.flatnonzero(tmask == 0)
+    P[off[::3]] = 2
+    return tmask, P
+
+
+@pytest.mark.parametrize("g", SMALL[:5], ids=lambda g: g.name)
+@pytest.mark.parametrize("lambda_steps", [0, 4])
+def test_lambda_max_is_the_largest_rayleigh_quotient_over_vectors(g, lambda_steps):
+    """Sec. IV-C.1: the estimate is the largest of the k Rayleigh quotients
+    h_j'L_G h_j / h_j'L_P h_j (eqs. 2, 4) of the power vectors, computed here from
+    dense matrices; with lambda_steps > t the same vectors continue."""
+    k, t = 6, 2
+    for inP in _subgraphs(g):
+        st = O.embed(g, inP, k=k, t=t, seed=3, pass_=2, lambda_steps=lambda_steps).stats
+        h = _dense_power_vectors(g, inP, k, max(t, lambda_steps), 3, 2)
+        LG, LP = dense_laplacian(g), dense_laplacian(g, inP)
+        rq = np.einsum("ij,ij->j", h, LG @ h) / np.einsum("ij,ij->j", h, LP @ h)
+        assert st["lambda_max"] == pytest.approx(rq.max(), rel=1e-9)
+        if not np.all(inP != 0):
+            # the k quotients differ, so an aggregate other than the maximum would fail
+            assert rq.max() > rq.mean() * (1 + 1e-6)
+
+
+@pytest.mark.parametrize("g", SMALL, ids=lambda g: g.name)
+def test_lambda_min_is_the_smallest_degree_ratio(g):
+    """eq. (61): lambda_min is estimated by min over nodes of L_G(v,v) / L_P(v,v),
+    the diagonals taken from scipy's graph Laplacians."""
+    for inP in _subgraphs(g):
+        st = O.embed(g, inP, k=2, t=1, seed=0).stats
+        ratio = np.diag(dense_laplacian(g)) / np.diag(dense_laplacian(g, inP))
+        assert st["lambda_min"] == pytest.approx(ratio.min(), rel=1e-12)
+        if not np.all(inP != 0):
+            assert ratio.max() > ratio.min() * (1 + 1e-9)  # only the minimum passes
+
+
+@pytest.mark.parametrize("n", [5, 9, 16])
+def test_lambda_min_of_a_cycle_against_its_path(n):
+    """Closed form: a unit n-cycle has degree 2 everywhere; its path has degree 1
+    at the two ends and 2 inside, so the degree ratios are 1 (inside) and 2 (ends)
+    and the eq. (61) estimate is 1, the true lambda_min of this pencil."""
+    g = G.cycle(n)
+    tmask = O.max_spanning_tree(g)
+    st = O.embed(g, tmask, k=2, t=1).stats
+    assert st["lambda_min"] == 1.0
+    assert np.sort(pencil_eigs(g, tmask))[0] == pytest.approx(1.0, abs=1e-9)
+
+
+def _hand_graph():
+    """Six nodes; the path 0-1-2-3-4-5 is the tree and five chords are off-tree:
+    (0,2) (0,5) (1,3) (2,4) (3,5). Canonical order (src < dst, sorted)."""
+    e = [(0, 1), (0, 2), (0, 5), (1, 2), (1, 3), (2, 3), (2, 4), (3, 4), (3, 5), (4, 5)]
+    src = np.array([a for a, _ in e], np.int32)
+    dst = np.array([b for _, b in e], np.int32)
+    g = G.Graph(6, src, dst, np.ones(len(e)), "hand6")
+    tree = np.array([1 if (b - a) == 1 else 0 for a, b in e], np.uint8)
+    heat = np.zeros(len(e))
+    for (a, b), h in {(0, 2): 10.0, (3, 5): 9.0, (1, 3): 8.0, (2, 4): 7.0, (0, 5): 6.0}.items():
+        heat[e.index((a, b))] = h
+    return g, e, tree, heat
+
+
+@pytest.mark.parametrize(
+    "sim_hops,budget,theta,expect",
+    [
+        # worked by hand from the reading of Sec. IV-D step 6: taking (0,2) marks 0, 2
+        # and their G-neighbours {1, 2, 5} and {0, 1, 3, 4}: every node, so no other
+        # chord is dissimilar
+        (1, 0, 0.5, [(0, 2)]),
+        # endpoint marks only: (3,5) and (1,3) and (2,4) each bring an unmarked
+        # endpoint; (0,5) then has both ends marked
+        (0, 0, 0.5, [(0, 2), (3, 5), (1, 3), (2, 4)]),
+        (0, 2, 0.5, [(0, 2), (3, 5)]),
+        # no similarity check: every candidate with heat >= 0.65 * 10 (eq. 58)
+        (-1, 0, 0.65, [(0, 2), (3, 5), (1, 3), (2, 4)]),
+    ],
+)
+def test_greedy_hand_worked_example(sim_hops, budget, theta, expect):
+    g, e, tree, heat = _hand_graph()
+    P, acc, nc = O.filter_select(g, heat, tree, theta, heat.max(), sim_hops=sim_hops, budget=budget)
+    got = sorted(e[i] for i in np.flatnonzero(P == 2))
+    assert got == sorted(expect) and acc == len(expect)
+
+
+@pytest.mark.parametrize("sim_hops", [0, 1])
+@pytest.mark.parametrize("budget", [0, 15])
+def test_greedy_defining_property(sim_hops, budget):
+    """Sec. IV-D step 6 under the reading of the similarity check: walking the
+    candidates in rank order (heat desc, id asc), an edge is taken exactly when at
+    least one endpoint is unmarked by the edges taken before it; a taken edge marks
+    its endpoints and, with sim_hops = 1, their neighbours in G; nothing is taken
+    once `budget` edges are in."""
+    g = G.random_connected(30, 200, seed=5)
+    tmask = O.max_spanning_tree(g)
+    rng = np.random.default_rng(9)
+    heat = np.round(rng.uniform(0, 10, g.m), 1)  # coarse values: ties by id occur
+    thr = 0.3
+    P, acc, nc = O.filter_select(g, heat, tmask, thr, heat.max(), sim_hops=sim_hops, budget=budget)
+    cand = np.flatnonzero((tmask == 0) & (heat >= thr * heat.max()))
+    order = cand[np.lexsort((cand, -heat[cand]))]
+    taken = set(np.flatnonzero(P == 2).tolist())
+    assert taken <= set(cand.tolist()) and nc == len(cand) and acc == len(taken)
+    A = adjacency(g).tolil().rows
+    marked = np.zeros(g.n, bool)
+    count, skipped_similar = 0, 0
+    for e in order:
+        p, q = int(g.src[e]), int(g.dst[e])
+        if budget and count == budget:
+            assert e not in taken
+            continue
+        if e in taken:
+            assert not (marked[p] and marked[q])
+            count += 1
+            marked[[p, q]] = True
+            if sim_hops >= 1:
+                marked[A[p]] = True
+                marked[A[q]] = True
+        else:
+            assert marked[p] and marked[q]
+            skipped_similar += 1
+    assert skipped_similar > 0  # the case exercises the similarity check
