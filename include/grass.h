@@ -53,8 +53,18 @@ typedef enum {
     GRASS_ERR_OOM = -3,         /* workspace too small / allocation failed */
     GRASS_ERR_DEVICE = -4,      /* HIP runtime error or a device-side guard tripped */
     GRASS_ERR_UNIMPLEMENTED = -5,
-    GRASS_ERR_CANCELLED = -6
+    GRASS_ERR_CANCELLED = -6,
+    GRASS_ERR_SOLVE = -7,       /* an L_P solve (eq. 29) ended above pcg_rtol, checked in FP64: the
+                                   pass's heats are not trusted, so nothing was selected from them;
+                                   grass_sparsify then stops with edge_mask = the subgraph before
+                                   that pass and a summary/trace of every pass run (the last one
+                                   flagged GRASS_PASS_SOLVE_FAILED); scores are undefined */
+    GRASS_ERR_NONFINITE = -8    /* a NaN or infinity appeared in the vectors, heats or residuals
+                                   (e.g. weights that overflow FP32 arithmetic); outputs undefined */
 } grass_status;
+
+/* grass_pass_stats.flags */
+enum { GRASS_PASS_SOLVE_FAILED = 1 };
 
 typedef struct grass_ctx grass_ctx;
 
@@ -105,6 +115,7 @@ typedef struct {
     int64_t pcg_iters;      /* inner PCG iterations summed over the pass's solves (max over vectors) */
     double pcg_resid64;     /* largest FP64 relative residual of the pass's L_P solves */
     double ms;              /* wall time of the pass */
+    int32_t flags;          /* GRASS_PASS_SOLVE_FAILED: pcg_resid64 > pcg_rtol (or not finite) */
 } grass_pass_stats;
 
 typedef struct {
@@ -133,7 +144,8 @@ size_t grass_workspace_bytes(int64_t n, int64_t m, const grass_opts *opts);
 
 /* The whole method: tree, passes of embedding + scoring + estimates, filtering
  * and densification until kappa <= sigma2 (Sec. IV-D). Returns GRASS_OK,
- * GRASS_NOT_CONVERGED or an error. */
+ * GRASS_NOT_CONVERGED, GRASS_ERR_SOLVE (a pass's L_P solve missed pcg_rtol; see
+ * the status) or another error. */
 grass_status grass_sparsify(grass_ctx *ctx, const grass_graph *g, const grass_opts *opts, void *workspace,
                             size_t ws_bytes, grass_result *res, void *stream);
 
@@ -216,7 +228,9 @@ grass_status grass_low_stretch_tree(grass_ctx *ctx, const grass_graph *g, uint64
  * the 1-edges must span G); pass = the Philox counter word of the start vectors.
  * heat: device [m], float32 or float64 per opts->precision, the unnormalized heat of
  * every edge (scaled by a power of two common to all edges: only ratios are
- * meaningful); stats: host, filled except candidates/accepted/theta. */
+ * meaningful); stats: host, filled except candidates/accepted/theta. Returns
+ * GRASS_ERR_SOLVE (heat written but not trusted; stats filled and flagged) when an
+ * L_P solve ended above pcg_rtol. */
 grass_status grass_embed(grass_ctx *ctx, const grass_graph *g, const uint8_t *p_mask, const grass_opts *opts,
                          int32_t pass, void *heat, grass_pass_stats *stats, void *workspace, size_t ws_bytes,
                          void *stream);

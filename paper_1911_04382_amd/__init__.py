@@ -18,14 +18,21 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "grass.h")
 
 OK, NOT_CONVERGED = 0, 1
 ERR_INVALID, ERR_DISCONNECTED, ERR_OOM, ERR_DEVICE, ERR_UNIMPLEMENTED, ERR_CANCELLED = -1, -2, -3, -4, -5, -6
+ERR_SOLVE, ERR_NONFINITE = -7, -8
+PASS_SOLVE_FAILED = 1
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_DISCONNECTED", -3: "ERR_OOM",
-                -4: "ERR_DEVICE", -5: "ERR_UNIMPLEMENTED", -6: "ERR_CANCELLED"}
+                -4: "ERR_DEVICE", -5: "ERR_UNIMPLEMENTED", -6: "ERR_CANCELLED", -7: "ERR_SOLVE",
+                -8: "ERR_NONFINITE"}
 
 
 class GrassError(RuntimeError):
-    def __init__(self, status, msg):
+    """A negative status. `result` carries what the call still returned (the
+    partial SparsifyResult of ERR_SOLVE, the stats of grass_embed), else None."""
+
+    def __init__(self, status, msg, result=None):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
         self.status = status
+        self.result = result
 
 
 class grass_graph(ctypes.Structure):
@@ -49,6 +56,7 @@ class grass_pass_stats(ctypes.Structure):
         ("kappa", ctypes.c_double), ("theta", ctypes.c_double), ("heat_max", ctypes.c_double),
         ("m_off", ctypes.c_int64), ("candidates", ctypes.c_int64), ("accepted", ctypes.c_int64),
         ("pcg_iters", ctypes.c_int64), ("pcg_resid64", ctypes.c_double), ("ms", ctypes.c_double),
+        ("flags", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -333,8 +341,14 @@ def grass_sparsify(ctx: Context, g: DeviceGraph, opts: grass_opts, ws=None, stre
                        ctypes.cast(tr, ctypes.POINTER(grass_pass_stats)), trace_cap)
     gc = g.c()
     wsp, wsb = _ws_args(ws)
-    rc = ctx.check(ctx.lib.grass_sparsify(ctx.h, ctypes.byref(gc), ctypes.byref(opts), wsp, wsb, ctypes.byref(res),
-                                          _stream_ptr(stream)))
+    rc = ctx.lib.grass_sparsify(ctx.h, ctypes.byref(gc), ctypes.byref(opts), wsp, wsb, ctypes.byref(res),
+                                _stream_ptr(stream))
+    if rc < 0:
+        part = None
+        if rc == ERR_SOLVE:  # the mask, summary and trace are still valid
+            part = SparsifyResult(rc, mask, None, summ.as_dict(),
+                                  [tr[i].as_dict() for i in range(min(summ.passes, trace_cap))])
+        raise GrassError(rc, ctx.last_error(), part)
     trace = [tr[i].as_dict() for i in range(min(summ.passes, trace_cap))]
     return SparsifyResult(rc, mask, scores, summ.as_dict(), trace)
 
@@ -476,9 +490,10 @@ def grass_embed(ctx: Context, g: DeviceGraph, p_mask, opts: grass_opts, pass_=0,
     st = grass_pass_stats()
     gc = g.c()
     wsp, wsb = _ws_args(ws)
-    ctx.check(ctx.lib.grass_embed(ctx.h, ctypes.byref(gc), ctypes.c_void_p(p_mask.data_ptr()), ctypes.byref(opts),
-                                  pass_, ctypes.c_void_p(heat.data_ptr()), ctypes.byref(st), wsp, wsb,
-                                  _stream_ptr(stream)))
+    rc = ctx.lib.grass_embed(ctx.h, ctypes.byref(gc), ctypes.c_void_p(p_mask.data_ptr()), ctypes.byref(opts), pass_,
+                             ctypes.c_void_p(heat.data_ptr()), ctypes.byref(st), wsp, wsb, _stream_ptr(stream))
+    if rc < 0:
+        raise GrassError(rc, ctx.last_error(), st.as_dict() if rc == ERR_SOLVE else None)
     return heat, st.as_dict()
 
 

@@ -122,6 +122,14 @@ Arena bind_arena(grass_ctx *ctx, void *ws, size_t ws_bytes, size_t need) {
 void check_device_flags(Topo &t, hipStream_t s) {
     unsigned f = (unsigned)read_i32(reinterpret_cast<const int *>(t.devflags), s);
     require(!(f & DEVERR_SPIN), GRASS_ERR_DEVICE, "a bounded device wait expired (tree-solve look-back)");
+    require(!(f & DEVERR_NONFINITE), GRASS_ERR_NONFINITE,
+            "a NaN or infinity appeared in the power vectors or heats (the working precision overflowed)");
+}
+
+// An L_P solve that ended above its FP64 target (or with a non-finite residual)
+bool solve_failed(double resid64, const grass_opts &o) {
+    const double rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
+    return !(resid64 <= rtol);
 }
 
 // Setup shared by every entry point: validation, CSR, subgraph mask, tree layout.
@@ -221,6 +229,7 @@ grass_status sparsify_impl(grass_ctx *ctx, const grass_graph &g, const grass_opt
     PassResult pr;
     int pass = 0;
     double kappa = 0;
+    bool failed = false;
     for (;; pass++) {
         auto t0 = std::chrono::steady_clock::now();
         pr = run_pass<T>(S, o, pass, added > 0, S.v.heat, s);
@@ -238,6 +247,12 @@ grass_status sparsify_impl(grass_ctx *ctx, const grass_graph &g, const grass_opt
         ps.m_off = m_off;
         ps.pcg_iters = pr.pcg_iters;
         ps.pcg_resid64 = pr.resid64;
+        if (added > 0 && solve_failed(pr.resid64, o)) {
+            // heats from an inaccurate solve are not trusted: select nothing from them
+            ps.flags |= GRASS_PASS_SOLVE_FAILED;
+            failed = true;
+            stop = true;
+        }
         if (!stop) {
             ps.theta = theta_of(o.sigma2, pr.sc.lambda_min, pr.sc.lambda_max, o.t);
             SelectOut so;
@@ -251,7 +266,7 @@ grass_status sparsify_impl(grass_ctx *ctx, const grass_graph &g, const grass_opt
             added += so.accepted;
             build_pcsr<T>(t, S.v, s);
             S.d.p_nnz = read_i32(t.prow + t.n, s);
-        } else if (!filtered && scores) {
+        } else if (!filtered && scores && !failed) {
             normalized_scores<T>(t, S.v.heat, pr.sc.heat_max, scores, s);
         }
         GR_HIP(hipStreamSynchronize(s));
@@ -274,6 +289,9 @@ grass_status sparsify_impl(grass_ctx *ctx, const grass_graph &g, const grass_opt
         sm.scored_edges = scored;
         sm.pcg_iters = pcg_total;
     }
+    if (failed)
+        throw Error(GRASS_ERR_SOLVE, "pass " + std::to_string(pass) + ": an L_P solve ended at FP64 relative residual " +
+                                         std::to_string(pr.resid64) + " > pcg_rtol; edge_mask holds the subgraph before it");
     return kappa <= o.sigma2 ? GRASS_OK : GRASS_NOT_CONVERGED;
 }
 
@@ -368,8 +386,12 @@ grass_status embed_impl(grass_ctx *ctx, const grass_graph &g, const uint8_t *p_m
         ps.pcg_iters = pr.pcg_iters;
         ps.pcg_resid64 = pr.resid64;
         ps.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (cnt[1] > 0 && solve_failed(pr.resid64, o)) ps.flags |= GRASS_PASS_SOLVE_FAILED;
         *stats = ps;
     }
+    if (cnt[1] > 0 && solve_failed(pr.resid64, o))
+        throw Error(GRASS_ERR_SOLVE, "an L_P solve ended at FP64 relative residual " + std::to_string(pr.resid64) +
+                                         " > pcg_rtol");
     return GRASS_OK;
 }
 

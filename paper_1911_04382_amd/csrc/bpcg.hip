@@ -328,9 +328,11 @@ __global__ __launch_bounds__(kLapGramThreads) void k_lap_gram(long long n, int k
                                                        const int *__restrict__ edeg, const float *__restrict__ P,
                                                        float *__restrict__ Q, int root, const float *__restrict__ R,
                                                        Tail<float> tl) {
-    constexpr int NT = kLapGramThreads, G = NT / KP, NIT = LapShape<E>::NIT, RPB = G * NIT;
+    constexpr int NT = kLapGramThreads, G = NT / KP, NIT = LapShape<KP>::NIT, RPB = G * NIT;
     constexpr int KK = KP * KP;
+    using L = LapTile<float, KP, E>;
     __shared__ double s_w[2 * KK];
+    __shared__ __align__(16) char lds[(NT / 64) * L::SLICE];
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;
     const bool act = j < k;
     BlockGram<float, KP, true> gq, gr;
@@ -345,28 +347,28 @@ __global__ __launch_bounds__(kLapGramThreads) void k_lap_gram(long long n, int k
     const long long xs = std::min(ntile, (long long)(blockIdx.x & 7) * per), xe = std::min(ntile, xs + per);
     // software pipeline: the next tile's neighbour lists are loaded while this
     // tile's second round (issued first) is in flight
-    LapCols<E> cur, nxt;
-    if (xs + q < xe) lap_load<KP, E, NT>((xs + q) * RPB, n, ecol, cur);
+    LapStage<float, KP, E> cur, nxt;
+    if (xs + q < xe) lap_load<float, KP, E>((xs + q) * RPB, n, ecol, eval, edeg, cur);
     for (long long t = xs + q; t < xe; t += nq) {
         const long long r0 = t * RPB;
-        LapFetch<float, E> F;
+        LapFetch<float, KP, E> F;
         float rv[NIT];
-        lap_fetch<float, KP, E, NT>(r0, n, k, eval, edeg, P, cur, F);
+        lap_fetch<float, KP, E>(r0, n, k, P, cur, lds, F);
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
-            const long long v = r0 + g + it * G;
+            const long long v = L::row(r0, g, it);
             // R streams through once here: a non-temporal load leaves L2 to the rows
             // of P that neighbouring tiles gather again (186 -> 183 us). Non-temporal
             // padded-row loads gained 1 us more but fetch each 128-byte line again for
             // every 8 rows; a non-temporal store of Q cost the R update its cache hits
             rv[it] = __builtin_nontemporal_load(&R[act && v < n ? v * k + j : 0]);
         }
-        if (t + nq < xe) lap_load<KP, E, NT>((t + nq) * RPB, n, ecol, nxt);
+        if (t + nq < xe) lap_load<float, KP, E>((t + nq) * RPB, n, ecol, eval, edeg, nxt);
         float xo[NIT], yo[NIT];
-        lap_rows<float, KP, E, NT>(r0, n, k, rowptr, col, val, ltail, P, Q, root, 1.f, F, xo, yo);
+        lap_rows<float, KP, E>(r0, n, k, rowptr, col, val, ltail, P, Q, root, 1.f, F, lds, xo, yo);
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
-            const bool ok = act && r0 + g + it * G < n;
+            const bool ok = act && L::row(r0, g, it) < n;
             gq.add(xo[it], yo[it]);
             gr.add(xo[it], ok ? rv[it] : 0.f);
         }
@@ -754,7 +756,7 @@ static void launch_gram(const Dims &d, const T *A, const T *B, const T *C, const
 template <typename T, int KP>
 static void launch_lap_gram(Topo &t, Vecs<T> &v, const Dims &d, int root, const Tail<T> &tl, hipStream_t s) {
     if constexpr (UseMF<T, KP>::value) {
-        constexpr long long RPB = (kLapGramThreads / KP) * LapShape<kEllP>::NIT;
+        constexpr long long RPB = (kLapGramThreads / KP) * LapShape<KP>::NIT;
         // one resident wave of blocks (each walks a range of tiles): more would
         // leave a second, partial wave behind
         static const int resident = [] {

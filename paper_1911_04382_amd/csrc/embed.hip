@@ -16,7 +16,8 @@ namespace grass {
 namespace {
 
 constexpr int kGaussBlocksMax = 2048;
-constexpr int kEdgesPerGroup = 16;  // scored edges per lane group
+constexpr bool kLapNTStore = true;    // the 16-byte-lane product stores y non-temporally
+constexpr int kScoreBlocksMax = 4096;  // scoring grid cap (each block then walks several rounds)
 
 // ------------------------------------------------------------ start vectors
 // Philox4x64-10 of Salmon et al. (SC'11); counter (v, j, pass, 0), key (seed, 0).
@@ -111,14 +112,15 @@ __global__ __launch_bounds__(kThreads) void k_lap(long long n, int k, const int 
                                                   const unsigned long long *__restrict__ scale_from,
                                                   double *__restrict__ dot_part, int nblk) {
     constexpr int G = kThreads / KP;
-    constexpr int NIT = LapShape<E>::NIT;
+    constexpr int NIT = LapShape<KP>::NIT;
     constexpr int RPB = G * NIT;
+    __shared__ __align__(16) char lds[(kThreads / 64) * LapTile<T, KP, E>::SLICE];
     int b = xcd_block(blockIdx.x, gridDim.x);
     if (b >= nblk) return;
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;
     T xo[NIT], yo[NIT];
     lap_tile<T, KP, E>((long long)b * RPB, n, k, rowptr, col, val, ltail, ecol, eval, edeg, x, y, root,
-                       (T)pow2_scale(scale_from), xo, yo);
+                       (T)pow2_scale(scale_from), lds, xo, yo);
     if (dot_part) {
         double dacc = 0.0;
 #pragma unroll
@@ -641,37 +643,114 @@ __global__ void k_solve_begin(int *__restrict__ tickets, unsigned *__restrict__ 
 }
 
 // ------------------------------------------------------------ scoring
-template <typename T, int KP>
-__global__ __launch_bounds__(kThreads) void k_score(long long m, int k, const int *__restrict__ src,
+// Edge heat w_pq sum_j (h_j[p] - h_j[q])^2 (eqs. 31, 35, 55) with the FP64
+// per-vector sums over E and over P (eqs. 2, 4) and the largest heat off P.
+// A lane group of KP lanes (lane j = vector j) takes KP consecutive edges per
+// round: lane i loads edge i's endpoints, weight and mask byte (coalesced) into
+// LDS. The group then works through the round in batches of SB edges: every
+// lane gathers column j of both H rows of the batch's edges at once (no load
+// waits on another), adds its FP64 terms to the column sums, and a
+// reduce-scatter over log2(SB) lane bits followed by a plain reduction over the
+// rest leaves each run of KP/SB lanes with the heat of one edge. Column sums add
+// the edges in id order within a lane group, and the groups and blocks in index
+// order: the result does not depend on timing.
+template <typename T>
+__device__ __forceinline__ T ld_u32off(const T *__restrict__ base, unsigned byte_off) {
+    // element at a 32-bit byte offset (arrays under 4 GiB): the load then takes the
+    // scalar-base plus 32-bit vector-offset form
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
+template <typename T, int KP, bool WIDE>
+__global__ __launch_bounds__(kThreads) void k_score(long long m, int k, int rounds, int nblk, const int *__restrict__ src,
                                                     const int *__restrict__ dst, const T *__restrict__ wT,
                                                     const uint8_t *__restrict__ mask, const T *__restrict__ H,
                                                     T *__restrict__ heat, double *__restrict__ part,
-                                                    unsigned long long *__restrict__ hmax) {
+                                                    unsigned long long *__restrict__ hmax,
+                                                    unsigned *__restrict__ devflags) {
     constexpr int G = kThreads / KP;
-    constexpr int EPB = G * kEdgesPerGroup;
+    constexpr int SB = KP < 16 ? KP : 16;  // edges per gather batch (8 -> 16: 104 -> 97 us on C2)
+    constexpr int RUN = KP / SB;         // lanes that end with the same edge's heat
+    __shared__ int s_p[G][KP], s_q[G][KP];
+    __shared__ T s_w[G][KP], s_wp[G][KP];  // weight; weight if the edge is in P, else 0
     __shared__ double s_num[G][KP];
     __shared__ double s_den[G][KP];
     __shared__ double s_max[kThreads / 64];
-    int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    const int g = threadIdx.x / KP, j = threadIdx.x % KP;
     const bool act = j < k;
+    const int jj = act ? j : 0;  // inactive lanes load a valid column and discard it
+    // the edge of the batch whose heat this lane ends with: lane bits, high to low
+    const int eb = j / RUN;
     double num = 0.0, den = 0.0, hm = 0.0;
-    long long e0 = (long long)blockIdx.x * EPB;
-    for (int i = g; i < EPB; i += G) {
-        long long e = e0 + i;
-        if (e >= m) break;
-        int p = src[e], q = dst[e];
-        T w = wT[e];
-        bool inP = mask[e] != 0;
-        T d = act ? (T)(H[(long long)p * k + j] - H[(long long)q * k + j]) : (T)0;
-        T sq = d * d;
+    bool bad = false;
+    // each XCD scores a contiguous eighth of the edges, so the rows of H that its
+    // edges share stay in that XCD's L2
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    for (int r = 0; r < (b < nblk ? rounds : 0); r++) {
+        const long long e0 = ((long long)b * rounds + r) * kThreads + (long long)g * KP;
+        if (e0 >= m) break;  // uniform over the lane group
+        {
+            const long long e = e0 + j;
+            const long long ee = e < m ? e : m - 1;
+            const T w = e < m ? wT[ee] : (T)0;  // past m: no term, no heat
+            s_p[g][j] = src[ee];
+            s_q[g][j] = dst[ee];
+            s_w[g][j] = w;
+            s_wp[g][j] = mask[ee] ? w : (T)0;
+        }
+        // the group is part of one wave: its LDS writes are seen by its later reads
+        __builtin_amdgcn_wave_barrier();
+        // one batch in flight per wave: unrolled batches would hold every batch's
+        // loads at once (160+ registers at KP = 32)
+#pragma unroll 1
+        for (int b0 = 0; b0 < KP; b0 += SB) {
+            T hp[SB], hq[SB], v[SB];
 #pragma unroll
-        for (int off = KP / 2; off >= 1; off >>= 1) sq += __shfl_xor(sq, off, 64);
-        T h = w * sq;
-        if (heat && j == 0) heat[e] = h;
-        double cw = (double)w * (double)d * (double)d;
-        num += cw;
-        if (inP) den += cw;
-        else hm = (double)h > hm ? (double)h : hm;
+            for (int i = 0; i < SB; i++) {
+                const int pi = s_p[g][b0 + i], qi = s_q[g][b0 + i];
+                if constexpr (WIDE) {
+                    hp[i] = H[(long long)pi * k + jj];
+                    hq[i] = H[(long long)qi * k + jj];
+                } else {
+                    hp[i] = ld_u32off(H, ((unsigned)pi * (unsigned)k + (unsigned)jj) * (unsigned)sizeof(T));
+                    hq[i] = ld_u32off(H, ((unsigned)qi * (unsigned)k + (unsigned)jj) * (unsigned)sizeof(T));
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SB; i++) {
+                const T di = act ? hp[i] - hq[i] : (T)0;
+                const double dd = (double)di;
+                num += (double)s_w[g][b0 + i] * dd * dd;
+                den += (double)s_wp[g][b0 + i] * dd * dd;  // + 0 off P: the same sum
+                v[i] = di * di;
+            }
+            // reduce-scatter: at offset o the lanes with bit o set keep the upper half
+            // of the remaining slots (values first: a conditional of the elements
+            // themselves would pick an address and index the array at run time)
+#pragma unroll
+            for (int o = KP / 2, c = SB / 2; c >= 1; o >>= 1, c >>= 1) {
+                const bool hi = (j & o) != 0;
+#pragma unroll
+                for (int i = 0; i < c; i++) {
+                    const T lo = v[i], up = v[i + c];
+                    const T send = hi ? lo : up;
+                    const T keep = hi ? up : lo;
+                    v[i] = keep + __shfl_xor(send, o, KP);
+                }
+            }
+            // then the plain sum over the RUN lanes that hold the same edge
+#pragma unroll
+            for (int o = RUN / 2; o >= 1; o >>= 1) v[0] += __shfl_xor(v[0], o, KP);
+            const long long e = e0 + b0 + eb;
+            if (j % RUN == 0 && e < m) {
+                const T w = s_w[g][b0 + eb];
+                const T h = w * v[0];
+                if (heat) heat[e] = h;
+                if (!__builtin_isfinite((double)h)) bad = true;
+                if (s_wp[g][b0 + eb] == (T)0) hm = (double)h > hm ? (double)h : hm;  // off P (w > 0)
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     s_num[g][j] = num;
     s_den[g][j] = den;
@@ -680,20 +759,155 @@ __global__ __launch_bounds__(kThreads) void k_score(long long m, int k, const in
         hm = o > hm ? o : hm;
     }
     if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = hm;
-    __syncthreads();
+    const bool anybad = __syncthreads_or(bad);
     if (g == 0) {
-        double a = 0.0, b = 0.0;
+        double a = 0.0, c = 0.0;
         for (int q = 0; q < G; q++) {
             a += s_num[q][j];
-            b += s_den[q][j];
+            c += s_den[q][j];
         }
-        part[(long long)blockIdx.x * 2 * KP + j] = a;
-        part[(long long)blockIdx.x * 2 * KP + KP + j] = b;
+        if (b < nblk) {
+            part[(long long)b * 2 * KP + j] = a;
+            part[(long long)b * 2 * KP + KP + j] = c;
+        }
     }
     if (threadIdx.x == 0) {
         double m2 = 0.0;
         for (int w = 0; w < kThreads / 64; w++) m2 = s_max[w] > m2 ? s_max[w] : m2;
         if (m2 > 0.0) atomicMax(hmax, (unsigned long long)__double_as_longlong(m2));
+        if (anybad) atomicOr(devflags, DEVERR_NONFINITE);
+    }
+}
+
+// The scorer with rows as 16-byte slices (k a power of two of at least W values,
+// as k_lapv): a row group of LPR = k / W lanes takes 8 edges per round; lane c
+// gathers the c-th slice of both endpoint rows of all 8 edges at once, adds its
+// W columns' FP64 terms, and a reduce-scatter over the group's lanes (then a plain
+// sum over any remaining lanes) leaves each lane with whole edges' heats.
+template <typename T, int KP>
+struct ScoreV {
+    static constexpr int W = V16<T>::W, LPR = KP / W, SB = 8;
+    static constexpr int G = kThreads / LPR;                       // row groups per block
+    static constexpr int RUN = LPR > SB ? LPR / SB : 1;            // lanes ending with one edge
+    static constexpr int M = LPR < SB ? SB / LPR : 1;              // edges ending in one lane
+    static constexpr int EPR = G * SB;                              // edges per block round
+};
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_scorev(long long m, int rounds, int nblk, const int *__restrict__ src,
+                                                     const int *__restrict__ dst, const T *__restrict__ wT,
+                                                     const uint8_t *__restrict__ mask, const T *__restrict__ H,
+                                                     T *__restrict__ heat, double *__restrict__ part,
+                                                     unsigned long long *__restrict__ hmax,
+                                                     unsigned *__restrict__ devflags) {
+    using S = ScoreV<T, KP>;
+    using V = typename V16<T>::type;
+    constexpr int W = S::W, LPR = S::LPR, SB = S::SB, G = S::G, RUN = S::RUN, M = S::M;
+    __shared__ int s_p[G][SB], s_q[G][SB];
+    __shared__ T s_w[G][SB], s_wp[G][SB];  // weight; weight if the edge is in P, else 0
+    __shared__ double s_num[G][KP];
+    __shared__ double s_den[G][KP];
+    __shared__ double s_max[kThreads / 64];
+    const int g = threadIdx.x / LPR, c = threadIdx.x % LPR;
+    double num[W], den[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) num[w] = den[w] = 0.0;
+    double hm = 0.0;
+    bool bad = false;
+    const V *Hs = reinterpret_cast<const V *>(H);
+    // each XCD scores a contiguous eighth of the edges, so the rows of H that its
+    // edges share stay in that XCD's L2
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    for (int r = 0; r < (b < nblk ? rounds : 0); r++) {
+        const long long e0 = ((long long)b * rounds + r) * S::EPR + (long long)g * SB;
+        if (e0 >= m) break;  // uniform over the row group
+#pragma unroll
+        for (int i = c; i < SB; i += LPR) {
+            const long long e = e0 + i, ee = e < m ? e : m - 1;
+            const T w = e < m ? wT[ee] : (T)0;  // past m: no term, no heat
+            s_p[g][i] = src[ee];
+            s_q[g][i] = dst[ee];
+            s_w[g][i] = w;
+            s_wp[g][i] = mask[ee] ? w : (T)0;
+        }
+        __builtin_amdgcn_wave_barrier();  // the group is part of one wave
+        V hp[SB], hq[SB];
+#pragma unroll
+        for (int i = 0; i < SB; i++) {
+            hp[i] = Hs[(long long)s_p[g][i] * LPR + c];
+            hq[i] = Hs[(long long)s_q[g][i] * LPR + c];
+        }
+        T sq[SB];
+#pragma unroll
+        for (int i = 0; i < SB; i++) {
+            const V dv = hp[i] - hq[i];
+            const double wi = (double)s_w[g][i], wpi = (double)s_wp[g][i];
+            T acc = (T)0;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                const double dd = (double)dv[w];
+                num[w] += wi * dd * dd;
+                den[w] += wpi * dd * dd;  // + 0 off P: the same sum
+                acc += dv[w] * dv[w];
+            }
+            sq[i] = acc;
+        }
+        // reduce-scatter over the group's lanes: at offset o the lanes with bit o set
+        // keep the upper half of the remaining slots (values first: a conditional of
+        // the elements themselves would index the array at run time)
+#pragma unroll
+        for (int o = LPR / 2, cnt = SB / 2; o >= 1 && cnt >= M; o >>= 1, cnt >>= 1) {
+            const bool hi = (c & o) != 0;
+#pragma unroll
+            for (int i = 0; i < cnt; i++) {
+                const T lo = sq[i], up = sq[i + cnt];
+                const T send = hi ? lo : up;
+                const T keep = hi ? up : lo;
+                sq[i] = keep + __shfl_xor(send, o, LPR);
+            }
+        }
+#pragma unroll
+        for (int o = RUN / 2; o >= 1; o >>= 1) sq[0] += __shfl_xor(sq[0], o, LPR);
+        if (c % RUN == 0) {
+#pragma unroll
+            for (int mm = 0; mm < M; mm++) {
+                const int i = (c / RUN) * M + mm;  // this lane's edge within the round
+                const long long e = e0 + i;
+                if (e < m) {
+                    const T h = s_w[g][i] * sq[mm];
+                    if (heat) heat[e] = h;
+                    if (!__builtin_isfinite((double)h)) bad = true;
+                    if (s_wp[g][i] == (T)0) hm = (double)h > hm ? (double)h : hm;  // off P (w > 0)
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        s_num[g][c * W + w] = num[w];
+        s_den[g][c * W + w] = den[w];
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        double o = __shfl_xor(hm, off, 64);
+        hm = o > hm ? o : hm;
+    }
+    if ((threadIdx.x & 63) == 0) s_max[threadIdx.x >> 6] = hm;
+    const bool anybad = __syncthreads_or(bad);
+    if (threadIdx.x < KP && b < nblk) {
+        const int j = threadIdx.x;
+        double a = 0.0, d2 = 0.0;
+        for (int q = 0; q < G; q++) {
+            a += s_num[q][j];
+            d2 += s_den[q][j];
+        }
+        part[(long long)b * 2 * KP + j] = a;
+        part[(long long)b * 2 * KP + KP + j] = d2;
+    }
+    if (threadIdx.x == 0) {
+        double m2 = 0.0;
+        for (int w = 0; w < kThreads / 64; w++) m2 = s_max[w] > m2 ? s_max[w] : m2;
+        if (m2 > 0.0) atomicMax(hmax, (unsigned long long)__double_as_longlong(m2));
+        if (anybad) atomicOr(devflags, DEVERR_NONFINITE);
     }
 }
 
@@ -860,12 +1074,19 @@ __global__ void k_absmax(long long nk, const T *__restrict__ x, unsigned long lo
 
 // ============================================================= host side
 
-static int lap_rows_per_block(int kp, int E = 8) {
-    return (kThreads / kp) * (E <= 4 ? LapShape<4>::NIT : LapShape<8>::NIT);
-}
-static int lap_blocks(const Dims &d, int E = 8) { return div_up(d.n, lap_rows_per_block(d.kp, E)); }
+static int lap_rows_per_block(int kp) { return (kThreads / kp) * lap_nit(kp); }
+static int lap_blocks(const Dims &d) { return div_up(d.n, lap_rows_per_block(d.kp)); }
 
-static int score_blocks(const Dims &d) { return div_up(d.m, (kThreads / d.kp) * kEdgesPerGroup); }
+// a round of a scoring block is kThreads consecutive edges (KP per lane group)
+// edges per block round: kThreads for the scalar scorer, ScoreV::EPR for the
+// 16-byte-lane one (used when k is a power of two of at least 16 bytes)
+static int score_epr(const Dims &d) {
+    const int W = d.prec == 64 ? 2 : 4;
+    if (d.k != d.kp || d.kp < W) return kThreads;
+    return (kThreads / (d.kp / W)) * 8;
+}
+static int score_rounds(const Dims &d) { return div_up(div_up(d.m, score_epr(d)), kScoreBlocksMax); }
+static int score_blocks(const Dims &d) { return div_up(div_up(d.m, score_epr(d)), score_rounds(d)); }
 static int gauss_blocks(const Dims &d) {
     return (int)std::min<long long>(kGaussBlocksMax, div_up(d.n, kThreads / d.kp));
 }
@@ -943,19 +1164,38 @@ void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, co
 template <typename T>
 void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x, T *y,
                int root, const unsigned long long *scale_from, double *dot_part, hipStream_t s) {
-    const int nb = lap_blocks(d, ell.E);
+    const int nb = lap_blocks(d);
     ProfScope ps(root < 0 ? PK_SPMM_G : PK_SPMM_P,
                  4.0 * (d.n + 1) + (double)(root < 0 ? 2 * d.m : d.p_nnz) * (4 + sizeof(T)) +
                      2.0 * d.n * d.k * sizeof(T),
                  s);
     lap_long<T>(d, rowptr, col, val, ell, x, s);
     KP_DISPATCH(d.kp, {
-        if (ell.E == kEllP)
-            hipLaunchKernelGGL((k_lap<T, KP, kEllP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col,
-                               val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
-        else
-            hipLaunchKernelGGL((k_lap<T, KP, kEllG>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col,
-                               val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
+        bool done = false;
+        if constexpr (lapv_ok<T, KP>()) {
+            // rows of whole 16-byte slices (k a power of two): the vector-lane kernel
+            if (d.k == KP && dot_part == nullptr) {
+                constexpr int RPB = 4 * (64 / (KP / V16<T>::W));
+                const int nv = div_up(d.n, RPB);
+                if (ell.E == kEllP)
+                    hipLaunchKernelGGL((k_lapv<T, KP, kEllP, kLapNTStore>), dim3(xcd_grid(nv)), dim3(256), 0, s, d.n,
+                                       rowptr, col, val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from,
+                                       nv);
+                else
+                    hipLaunchKernelGGL((k_lapv<T, KP, kEllG, kLapNTStore>), dim3(xcd_grid(nv)), dim3(256), 0, s, d.n,
+                                       rowptr, col, val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from,
+                                       nv);
+                done = true;
+            }
+        }
+        if (!done) {
+            if (ell.E == kEllP)
+                hipLaunchKernelGGL((k_lap<T, KP, kEllP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr,
+                                   col, val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
+            else
+                hipLaunchKernelGGL((k_lap<T, KP, kEllG>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr,
+                                   col, val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
+        }
     });
     GR_CHECK_LAUNCH();
 }
@@ -1059,6 +1299,8 @@ double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, bool fold, 
     double worst = 0.0;
     for (int j = 0; j < d.k; j++) {
         double bj = std::sqrt(hb[j]), rj = std::sqrt(hb[kMaxK + j]);
+        require(std::isfinite(bj) && std::isfinite(rj), GRASS_ERR_NONFINITE,
+                "a NaN or infinity appeared in an L_P solve (the working precision overflowed)");
         double rel = bj > 0 ? rj / bj : 0.0;
         worst = rel > worst ? rel : worst;
     }
@@ -1099,8 +1341,23 @@ void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStr
     fill_u32(reinterpret_cast<unsigned *>(v.u64s + U_HMAX), 2, 0u, s);
     ProfScope ps(PK_SCORE, (double)d.m * (9 + 2 * sizeof(T)) + (double)d.n * d.k * sizeof(T), s);
     KP_DISPATCH(d.kp, {
-        hipLaunchKernelGGL((k_score<T, KP>), dim3(nb), dim3(kThreads), 0, s, d.m, d.k, t.src, t.dst, v.wT, t.mask, H,
-                           heat, v.part, v.u64s + U_HMAX);
+        bool vec = false;
+        if constexpr (lapv_ok<T, KP>()) {
+            if (d.k == KP) {
+                if (ScoreV<T, KP>::EPR != score_epr(d)) throw Error(GRASS_ERR_DEVICE, "scorer round size mismatch");
+                hipLaunchKernelGGL((k_scorev<T, KP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m, score_rounds(d),
+                                   nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part, v.u64s + U_HMAX, t.devflags);
+                vec = true;
+            }
+        }
+        // 32-bit gather offsets while the n x k block is under 4 GiB
+        if (vec) {
+        } else if ((unsigned long long)d.n * d.k * sizeof(T) < (1ull << 32))
+            hipLaunchKernelGGL((k_score<T, KP, false>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m, d.k,
+                               score_rounds(d), nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part, v.u64s + U_HMAX, t.devflags);
+        else
+            hipLaunchKernelGGL((k_score<T, KP, true>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m, d.k,
+                               score_rounds(d), nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part, v.u64s + U_HMAX, t.devflags);
         GR_CHECK_LAUNCH();
         col_sum<T>(d, v, v.part, nb, 2 * KP, 0, v.red + RED_NUM * kMaxK, s);
         col_sum<T>(d, v, v.part, nb, 2 * KP, KP, v.red + RED_DEN * kMaxK, s);
