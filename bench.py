@@ -60,27 +60,99 @@ def workload(name: str):
     return g, cfg, desc
 
 
-def cpu_baseline(g, cfg, budget_s=30.0):
-    """The FP64 oracle (single thread) on a bounded sample of the same workload:
-    its tree pass (Kruskal + t tree-solve power steps on k vectors + scoring of
-    every off-tree edge) on the full graph."""
-    import oracle as O
+def host_cpu():
+    """nproc and the CPU model of the host (reported beside every oracle number)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
+
+def cpu_baseline(g, cfg, sample_side=30):
+    """The FP64 oracle (single thread) on a bounded sample of the same workload: the
+    whole method (tree, every densification pass with its tree / PCG solves,
+    scoring, filtering) on a sample_side^3 mesh of the same family and options,
+    like for like with the GPU's end-to-end value. Also its tree pass on the full
+    graph, whose heats serve the accuracy check. Returns (baseline dict, oracle
+    tree-pass heats, oracle tree-pass stats)."""
+    import oracle as O
+    from paper_1911_04382_amd import graphs as G
+
+    gs = G.config_c2(sample_side)
     t0 = time.perf_counter()
-    tree = O.max_spanning_tree(g)
+    r = O.sparsify(gs, sigma2=cfg["sigma2"], k=cfg["k"], t=cfg["t"], seed=0)
     t1 = time.perf_counter()
-    res = O.embed(g, tree, k=cfg["k"], t=cfg["t"], seed=0, pass_=0)
+    scored = sum(tr["m_off"] for tr in r.trace)
+    tree = O.max_spanning_tree(g)
     t2 = time.perf_counter()
+    res = O.embed(g, tree, k=cfg["k"], t=cfg["t"], seed=0, pass_=0)
+    t3 = time.perf_counter()
     m_off = int(res.stats["m_off"])
-    return {
-        "value": m_off / (t2 - t0),
+    base = {
+        "value": scored / (t1 - t0),
         "unit": "edges/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"oracle tree pass on the full graph: Kruskal {t1 - t0:.2f}s + embedding/scoring "
-                   f"{t2 - t1:.2f}s for {m_off} off-tree edges (k={cfg['k']}, t={cfg['t']}, FP64, 1 thread); "
-                   "later densification passes need PCG and cost the oracle more per edge"),
+        "sample": (f"oracle, whole sparsify call on a {sample_side}^3 mesh of the same family ({gs.n} nodes, "
+                   f"{gs.m} edges, k={cfg['k']}, t={cfg['t']}, sigma^2={cfg['sigma2']}, FP64, 1 thread): "
+                   f"{r.summary['passes']} passes, {scored} off-tree edges scored in {t1 - t0:.2f} s"),
+        "tree_pass_full_graph": {"value": m_off / (t3 - t2 + t2 - t1), "unit": "edges/s",
+                                 "sample": f"Kruskal {t2 - t1:.2f} s + embedding/scoring {t3 - t2:.2f} s on the full "
+                                           f"graph, {m_off} off-tree edges"},
+        **host_cpu(),
     }
+    return base, res.heat, res.stats
+
+
+def accuracy(grass, ctx, dg, g, cfg, heat_ora, st_ora):
+    """Error of the GPU tree pass (pass 0 of the timed workload, the benchmark's
+    precision and kernels) against the FP64 oracle's, on the full graph: normalized
+    scores s = heat / max off-tree heat (eq. 58), per-edge relative error for
+    edges with s_oracle >= 1e-5, and the lambda estimates."""
+    import numpy as np
+
+    tree = grass.grass_spanning_tree(ctx, dg)
+    heat, st = grass.grass_embed(ctx, dg, tree, grass.make_opts(**cfg), pass_=0)
+    h = heat.double().cpu().numpy()
+    off = tree.cpu().numpy() == 0
+    s_gpu = h / h[off].max()
+    s_ora = heat_ora / heat_ora[off].max()
+    d = np.abs(s_gpu - s_ora)[off]
+    big = off & (s_ora >= 1e-5)
+    rel = np.abs(s_gpu - s_ora)[big] / s_ora[big]
+    return {"what": "tree pass (pass 0) on the full graph against the FP64 oracle",
+            "score_err_max": float(d.max()), "score_rel_err_max": float(rel.max()),
+            "score_rel_err_p99": float(np.quantile(rel, 0.99)), "score_rel_err_median": float(np.median(rel)),
+            "rel_err_floor": 1e-5, "edges_above_floor": int(big.sum()),
+            "lambda_max_rel_err": abs(st["lambda_max"] - st_ora["lambda_max"]) / st_ora["lambda_max"],
+            "lambda_min_rel_err": abs(st["lambda_min"] - st_ora["lambda_min"]) / st_ora["lambda_min"]}
+
+
+def true_kappa(grass, ctx, dg, mask, cfg, steps=(50, 100)):
+    """lambda_max of the final sparsifier by continuing the power iteration
+    (Sec. IV-C.1) on one vector, FP64, to each step count in `steps` (two counts
+    show convergence), against the t-step estimate that stopped the loop.
+    lambda_min >= 1 for a subgraph (Sec. II-C) and <= the eq. (61) estimate. One
+    vector: after this many steps every vector of a block is the same dominant
+    eigenvector, and a block of identical right-hand sides leaves the block PCG
+    rank-deficient."""
+    out = {"vectors": 1, "precision": "f64"}
+    t0 = time.perf_counter()
+    for n in steps:
+        c = dict(cfg)
+        c.update(k=1, lambda_steps=n, precision=64)
+        _, st = grass.grass_embed(ctx, dg, mask, grass.make_opts(**c), pass_=1000)
+        out[f"lambda_max_{n}_steps"] = st["lambda_max"]
+        out["lambda_min_est"] = st["lambda_min"]
+    lm = out[f"lambda_max_{steps[-1]}_steps"]
+    out.update(kappa_upper=lm, kappa_lower=lm / out["lambda_min_est"], seconds=time.perf_counter() - t0)
+    return out
 
 
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
@@ -345,6 +417,11 @@ def run_partition(args, grass, torch):
 
 
 def run_serving(args, grass, torch):
+    line = serving_leg(args.count, args.c5_max_n, args.rho, args.workers, args.arena_gb, grass, torch)
+    print(json.dumps(line), flush=True)
+
+
+def serving_leg(count, max_n, rho, workers, arena_gb, grass, torch):
     """C5: a Poisson stream of sparsify requests on preferential-attachment graphs.
     Plain path: one request at a time in arrival order on one stream. Server:
     continuous batching with admission by workspace footprint. Both see the same
@@ -352,7 +429,7 @@ def run_serving(args, grass, torch):
     import numpy as np
     from paper_1911_04382_amd import graphs as G
 
-    sizes = G.config_c5_sizes(args.count, lo=1e4, hi=args.c5_max_n, seed=1)
+    sizes = G.config_c5_sizes(count, lo=1e4, hi=max_n, seed=1)
     gs = [G.config_c5_graph(int(n), seed=100 + i) for i, n in enumerate(sizes)]
     dgs = [grass.to_device(g, "cuda:0") for g in gs]
     opts = grass.make_opts(k=16, t=2, sigma2=100.0, precision=32)
@@ -368,11 +445,11 @@ def run_serving(args, grass, torch):
         service.append(time.perf_counter() - t0)
         log(f"plain path: request {i + 1}/{len(dgs)} (n={dg.n}) {service[-1] * 1e3:.0f} ms")
     mu = 1.0 / (sum(service) / len(service))
-    rate = args.rho * mu
+    rate = rho * mu
     rng = np.random.Generator(np.random.Philox(key=1))
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(dgs)))
     log(f"C5: {len(dgs)} requests, n in [{min(g.n for g in gs)}, {max(g.n for g in gs)}], mean service "
-        f"{1e3 / mu:.0f} ms, arrival rate {rate:.2f}/s (rho {args.rho})")
+        f"{1e3 / mu:.0f} ms, arrival rate {rate:.2f}/s (rho {rho})")
     # plain FIFO at these arrival times (simulated clock: service times measured above)
     clock, lat_plain = 0.0, []
     for a, sv in zip(arrivals, service):
@@ -380,7 +457,7 @@ def run_serving(args, grass, torch):
         lat_plain.append(clock - a)
     # the server, live
     need = max(grass.load_library().grass_workspace_bytes(d.n, d.m, opts) for d in dgs)
-    srv = grass.Server(ctx, max(need * args.workers, int(args.arena_gb * (1 << 30))), workers=args.workers)
+    srv = grass.Server(ctx, max(need * workers, int(arena_gb * (1 << 30))), workers=workers)
     t0 = time.perf_counter()
     tickets = []
     seen = [0]
@@ -413,15 +490,15 @@ def run_serving(args, grass, torch):
             "value": percentile(lat_srv, 0.99) * 1e3, "unit": "ms (p99, server)", "n_gpus": 1,
             "higher_is_better": False, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"C5: {len(dgs)} Barabasi-Albert requests (m=5), n from p(n)~n^-2 on "
-                                   f"[1e4, {args.c5_max_n:.0e}], U[0.1,1), k=16, t=2, sigma^2=100, Poisson arrivals at "
-                                   f"rho={args.rho} of plain capacity",
-                       "workers": args.workers, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
+                                   f"[1e4, {max_n:.0e}], U[0.1,1), k=16, t=2, sigma^2=100, Poisson arrivals at "
+                                   f"rho={rho} of plain capacity",
+                       "workers": workers, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
             "server_ms": {"p50": percentile(lat_srv, 0.5) * 1e3, "p99": percentile(lat_srv, 0.99) * 1e3},
             "plain_ms": {"p50": percentile(lat_plain, 0.5) * 1e3, "p99": percentile(lat_plain, 0.99) * 1e3},
             "server_edges_per_s": scored / makespan, "all_done": ok,
             "mean_service_ms": 1e3 / mu, "arrival_rate_per_s": rate}
     ctx.close()
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def main():
@@ -438,11 +515,15 @@ def main():
                          "kernel, or none")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (PMC calibration)")
-    ap.add_argument("--count", type=int, default=64, help="c4: graphs; c5: requests")
+    ap.add_argument("--count", type=int, default=256, help="c4: graphs; c5: requests")
     ap.add_argument("--workers", type=int, default=8, help="c4/c5: concurrent graphs")
     ap.add_argument("--rho", type=float, default=0.7, help="c5: arrival rate / plain-path capacity")
-    ap.add_argument("--c5-max-n", type=float, default=1e5, help="c5: largest request (nodes)")
+    ap.add_argument("--c5-max-n", type=float, default=2e6, help="c5: largest request (nodes)")
     ap.add_argument("--arena-gb", type=float, default=16.0, help="c5: server arena (GiB)")
+    ap.add_argument("--serve-count", type=int, default=16,
+                    help="default run: requests of the served-stream leg (C5 sizes and arrivals)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default run: skip the served-stream leg, the oracle accuracy check and the true kappa")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs a single graph (or batch) per device and has no "
@@ -451,7 +532,7 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.workload in ("c4", "c5"):
+    if args.workload in ("c4", "c5") or (args.workload == "c2" and not args.no_extras):
         # concurrent graphs need hardware queues beyond HIP's default of 4
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(16, max(4, args.workers)))
 
@@ -569,9 +650,32 @@ def main():
                         "alg_GBs": round(v["alg_bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] > 0 else None}
                     for k, v in (breakdown or {}).items() if v["launches"]},
     }
-    if not args.no_cpu_baseline:
-        log("timing the oracle tree pass on the host ...")
-        line["cpu_baseline"] = cpu_baseline(g, cfg)
+    extras = args.workload == "c2" and not args.no_extras
+    heat_ora = st_ora = None
+    if not args.no_cpu_baseline or extras:
+        log("timing the oracle on the host (whole call on a 30^3 mesh, tree pass on the full graph) ...")
+        base, heat_ora, st_ora = cpu_baseline(g, cfg)
+        if not args.no_cpu_baseline:
+            line["cpu_baseline"] = base
+    if extras:
+        log("accuracy of the tree pass against the oracle ...")
+        line["accuracy"] = accuracy(grass, ctx, dg, g, cfg, heat_ora, st_ora)
+        log(f"  {line['accuracy']}")
+        log("true kappa of the final sparsifier (50 continued power steps) ...")
+        line["true_kappa"] = true_kappa(grass, ctx, dg, r.mask, cfg)
+        line["true_kappa"]["kappa_est_t"] = summaries[-1]["kappa"]
+        log(f"  {line['true_kappa']}")
+        log(f"served-stream leg: {args.serve_count} C5 requests ...")
+        sv = serving_leg(args.serve_count, 2e6, args.rho, args.workers, args.arena_gb, grass, torch)
+        line["serving"] = {"workload": sv["config"]["workload"], "workers": sv["config"]["workers"],
+                           "server_ms": sv["server_ms"], "plain_ms": sv["plain_ms"],
+                           "server_edges_per_s": sv["server_edges_per_s"], "all_done": sv["all_done"],
+                           "mean_service_ms": sv["mean_service_ms"], "arrival_rate_per_s": sv["arrival_rate_per_s"],
+                           "plain_latency": "simulated from measured one-at-a-time service times at the same "
+                                            "arrival times"}
+        line["latency_ms"] = {"server": sv["server_ms"], "plain": sv["plain_ms"],
+                              "workload": "served-stream leg (C5 sizes), same arrival trace for both",
+                              "c2_call": line["latency_ms"]}
     ctx.close()
     print(json.dumps(line), flush=True)
 

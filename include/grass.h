@@ -94,10 +94,11 @@ typedef struct {
     int32_t sim_hops;       /* similarity marks: -1 off, 0 endpoints, 1 endpoints + neighbours [1] */
     int32_t lambda_steps;   /* power steps for lambda_max (>= t continues the vectors) [0 = t] */
     double pcg_rtol;        /* relative residual target of every L_P solve, checked in FP64 [1e-6] */
-    int32_t pcg_max_iters;  /* inner PCG iterations per refinement step [2000] */
-    double pcg_inner_rtol;  /* residual reduction of the working-precision block PCG between FP64
-                               refinement restarts [1e-2] */
-    int32_t pcg_max_outer;  /* FP64 refinement restarts per solve [20] */
+    int32_t pcg_max_iters;  /* working-precision block-PCG iterations per L_P solve, all inner solves
+                               together [2000] */
+    double pcg_inner_rtol;  /* residual reduction of each inner block-PCG solve between the FP64
+                               flexible-CG steps around it [1e-2] */
+    int32_t pcg_max_outer;  /* FP64 flexible-CG steps per L_P solve [50] */
     int32_t precision;      /* 32: FP32 vectors (FP64 sums); 64: FP64 throughout [32] */
     const uint8_t *init_mask; /* optional device [m]: 1 = edge of a caller-given spanning tree,
                                  2 = already-added edge, 0 = off; NULL = compute the tree */

@@ -126,6 +126,12 @@ void check_device_flags(Topo &t, hipStream_t s) {
             "a NaN or infinity appeared in the power vectors or heats (the working precision overflowed)");
 }
 
+std::string sci(double x) {
+    char b[32];
+    std::snprintf(b, sizeof(b), "%.3e", x);
+    return b;
+}
+
 // An L_P solve that ended above its FP64 target (or with a non-finite residual)
 bool solve_failed(double resid64, const grass_opts &o) {
     const double rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
@@ -291,7 +297,8 @@ grass_status sparsify_impl(grass_ctx *ctx, const grass_graph &g, const grass_opt
     }
     if (failed)
         throw Error(GRASS_ERR_SOLVE, "pass " + std::to_string(pass) + ": an L_P solve ended at FP64 relative residual " +
-                                         std::to_string(pr.resid64) + " > pcg_rtol; edge_mask holds the subgraph before it");
+                                         sci(pr.resid64) + " > pcg_rtol " + sci(o.pcg_rtol) +
+                                         "; edge_mask holds the subgraph before it");
     return kappa <= o.sigma2 ? GRASS_OK : GRASS_NOT_CONVERGED;
 }
 
@@ -390,8 +397,8 @@ grass_status embed_impl(grass_ctx *ctx, const grass_graph &g, const uint8_t *p_m
         *stats = ps;
     }
     if (cnt[1] > 0 && solve_failed(pr.resid64, o))
-        throw Error(GRASS_ERR_SOLVE, "an L_P solve ended at FP64 relative residual " + std::to_string(pr.resid64) +
-                                         " > pcg_rtol");
+        throw Error(GRASS_ERR_SOLVE, "an L_P solve ended at FP64 relative residual " + sci(pr.resid64) +
+                                         " > pcg_rtol " + sci(o.pcg_rtol));
     return GRASS_OK;
 }
 
@@ -506,7 +513,7 @@ grass_opts grass_opts_default(void) {
     o.pcg_rtol = 1e-6;
     o.pcg_max_iters = 2000;
     o.pcg_inner_rtol = 1e-2;
-    o.pcg_max_outer = 20;
+    o.pcg_max_outer = 50;
     o.precision = 32;
     o.init_mask = nullptr;
     return o;

@@ -852,7 +852,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     SolveInfo info;
     fill_i32(v.tcnt, bpcg_counters(d), 0, s);
     // r = b - L_P x with x = 0; its norms are the reference of the first inner phase
-    info.resid64 = true_residual<T>(t, v, d, b, false, s);
+    info.resid64 = true_residual<T>(t, v, d, b, s);
     if (info.resid64 <= pp.rtol) return info;
     // a fresh search block: P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
     auto start_block = [&]() {
@@ -878,6 +878,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     tcheck.count = cnt;
     tcheck.tol2 = pp.itol * pp.itol;
     long long it = 0;
+    bool fresh = true, checked = false;  // the next FCG step starts a recurrence; resid64 recomputed
     while (true) {
         it++;
         bool stop = false, restart = false;
@@ -899,12 +900,22 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
             const bool last = it >= pp.max_it;
             if (last || (it & 3) == 0) {
                 if (last || read_i32(cnt, s) == 0) {
-                    // every vector's recursive residual fell by itol since the last
-                    // refinement step: X += P alpha, fold X into the FP64 solution,
-                    // recompute the residual there and restart from it
+                    // every vector's recursive residual fell by itol since the inner
+                    // solve started: X += P alpha completes z ~ L_P^-1 r, which the FP64
+                    // flexible-CG step turns into its next direction; the inner solve
+                    // then restarts from the new FP64 residual
                     launch_rowmul<T, KP, true>(d, v.smallT + T_ALPHA * KK, v.p, v.dx, v.dx, s);
-                    info.resid64 = true_residual<T>(t, v, d, b, true, s);
-                    if (last || info.resid64 <= pp.rtol || info.outer >= pp.max_repl) stop = true;
+                    info.resid64 = fcg_outer_step<T>(t, v, d, fresh, s);
+                    fresh = false;
+                    checked = false;
+                    if (info.resid64 <= pp.rtol) {
+                        // the recurrence's residual drifts from b - L_P x by rounding: check
+                        // the recomputed one, and if it misses the target go on from it
+                        // with a fresh recurrence (residual replacement)
+                        info.resid64 = true_residual<T>(t, v, d, b, s);
+                        checked = fresh = true;
+                    }
+                    if (last || info.resid64 <= pp.rtol || info.outer + 1 >= pp.max_repl) stop = true;
                     else restart = true;
                 }
             }
@@ -933,7 +944,10 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
             start_block();
         }
     }
+    info.outer++;
     info.iters = it;
+    // the reported residual is always the one recomputed from the solution
+    if (!checked) info.resid64 = true_residual<T>(t, v, d, b, s);
     return info;
 }
 

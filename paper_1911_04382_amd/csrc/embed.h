@@ -7,8 +7,11 @@ namespace grass {
 
 // reduction slots in Vecs::red (kMaxK doubles each)
 enum : int {
-    RED_NUM = 0, RED_DEN, RED_LMAX, RED_PQ, RED_RZ, RED_RZN, RED_RR, RED_RR0, RED_ALPHA, RED_BETA,
-    RED_BN, RED_RN, RED_MEAN, RED_SCRATCH, RED_SLOTS = 16
+    RED_NUM = 0, RED_DEN, RED_LMAX, RED_RR, RED_BN, RED_RN, RED_MEAN,
+    // the FP64 flexible-CG outer iteration of the L_P solve (per column): z'A d_prev,
+    // d'r, d'A d, the previous d'A d, its alpha and beta
+    RED_ZAD, RED_DR, RED_DAD, RED_DADP, RED_FA, RED_FB,
+    RED_SLOTS = 16
 };
 // u64 slots in Vecs::u64s
 enum : int { U_HMAX = 0, U_LMIN = 1, U_ABSMAX = 2, U_SLOTS = 8 };
@@ -60,10 +63,15 @@ struct SolveInfo {
 template <typename T>
 SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s);
 
-// x64 += dx, dx = 0 when fold; r = b - L_P x64 in FP64 (stored in v.r), squared
-// norms in red[RED_RN]; returns max_j ||r_j|| / ||b_j|| (b norms in red[RED_BN]).
+// r = b - L_P x64 in FP64 (v.r64, and v.r rounded to T), squared norms in
+// red[RED_RN]; returns max_j ||r_j|| / ||b_j|| (b norms in red[RED_BN]).
 template <typename T>
-double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, bool fold, hipStream_t s);
+double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, hipStream_t s);
+// One FP64 flexible-CG step of the L_P solve with z = v.dx from the inner block PCG
+// (first: start the recurrence): x64, r64, v.r and the norms in red[RED_RN] are
+// updated, v.dx is cleared; returns max_j ||r_j|| / ||b_j||.
+template <typename T>
+double fcg_outer_step(Topo &t, Vecs<T> &v, const Dims &d, bool first, hipStream_t s);
 
 // Score every edge: heat (optional output), FP64 per-vector sums over E and over P,
 // max heat over the edges not in P. Then reduce to lambda_max (host reads).
@@ -84,7 +92,7 @@ void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride
 // x64 and dx hold zero and red[RED_BN] the squared norms of b on entry.
 struct PcgParams {
     double rtol = 1e-6, itol = 1e-2;
-    int max_it = 2000, max_repl = 20;
+    int max_it = 2000, max_repl = 50;
 };
 template <typename T>
 SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s);

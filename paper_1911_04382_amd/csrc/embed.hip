@@ -784,15 +784,18 @@ __global__ __launch_bounds__(kThreads) void k_score(long long m, int k, int roun
 // gathers the c-th slice of both endpoint rows of all 8 edges at once, adds its
 // W columns' FP64 terms, and a reduce-scatter over the group's lanes (then a plain
 // sum over any remaining lanes) leaves each lane with whole edges' heats.
+// edges per row group and round: 8 for rows of 8 or more lanes, else 4 (C2, k = 32:
+// 8 took 96 -> 85 us; C3, k = 16: 4 took 125 -> 110 us)
+constexpr int scorev_sb(int lpr) { return lpr >= 8 ? 8 : 4; }
 template <typename T, int KP>
 struct ScoreV {
-    static constexpr int W = V16<T>::W, LPR = KP / W, SB = 8;
+    static constexpr int W = V16<T>::W, LPR = KP / W, SB = scorev_sb(LPR);
     static constexpr int G = kThreads / LPR;                       // row groups per block
     static constexpr int RUN = LPR > SB ? LPR / SB : 1;            // lanes ending with one edge
     static constexpr int M = LPR < SB ? SB / LPR : 1;              // edges ending in one lane
     static constexpr int EPR = G * SB;                              // edges per block round
 };
-template <typename T, int KP>
+template <typename T, int KP, bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_scorev(long long m, int rounds, int nblk, const int *__restrict__ src,
                                                      const int *__restrict__ dst, const T *__restrict__ wT,
                                                      const uint8_t *__restrict__ mask, const T *__restrict__ H,
@@ -822,34 +825,43 @@ __global__ __launch_bounds__(kThreads) void k_scorev(long long m, int rounds, in
         if (e0 >= m) break;  // uniform over the row group
 #pragma unroll
         for (int i = c; i < SB; i += LPR) {
+            // the edge arrays stream through once: non-temporal loads leave L2 to H
             const long long e = e0 + i, ee = e < m ? e : m - 1;
-            const T w = e < m ? wT[ee] : (T)0;  // past m: no term, no heat
-            s_p[g][i] = src[ee];
-            s_q[g][i] = dst[ee];
+            const T w = e < m ? __builtin_nontemporal_load(&wT[ee]) : (T)0;  // past m: no term, no heat
+            s_p[g][i] = __builtin_nontemporal_load(&src[ee]);
+            s_q[g][i] = __builtin_nontemporal_load(&dst[ee]);
             s_w[g][i] = w;
-            s_wp[g][i] = mask[ee] ? w : (T)0;
+            s_wp[g][i] = __builtin_nontemporal_load(&mask[ee]) ? w : (T)0;
         }
         __builtin_amdgcn_wave_barrier();  // the group is part of one wave
         V hp[SB], hq[SB];
 #pragma unroll
         for (int i = 0; i < SB; i++) {
-            hp[i] = Hs[(long long)s_p[g][i] * LPR + c];
-            hq[i] = Hs[(long long)s_q[g][i] * LPR + c];
+            if constexpr (WIDE) {
+                hp[i] = Hs[(long long)s_p[g][i] * LPR + c];
+                hq[i] = Hs[(long long)s_q[g][i] * LPR + c];
+            } else {  // 32-bit byte offsets: no 64-bit address per load
+                hp[i] = ld_u32off(Hs, ((unsigned)s_p[g][i] * (unsigned)LPR + (unsigned)c) * 16u);
+                hq[i] = ld_u32off(Hs, ((unsigned)s_q[g][i] * (unsigned)LPR + (unsigned)c) * 16u);
+            }
         }
         T sq[SB];
+        V bn = (T)0, bd = (T)0;  // the batch's terms per column, added to the FP64 sums once
 #pragma unroll
         for (int i = 0; i < SB; i++) {
             const V dv = hp[i] - hq[i];
-            const double wi = (double)s_w[g][i], wpi = (double)s_wp[g][i];
+            const V d2 = dv * dv;
+            bn += s_w[g][i] * d2;
+            bd += s_wp[g][i] * d2;  // + 0 off P: the same sum
             T acc = (T)0;
 #pragma unroll
-            for (int w = 0; w < W; w++) {
-                const double dd = (double)dv[w];
-                num[w] += wi * dd * dd;
-                den[w] += wpi * dd * dd;  // + 0 off P: the same sum
-                acc += dv[w] * dv[w];
-            }
+            for (int w = 0; w < W; w++) acc += d2[w];
             sq[i] = acc;
+        }
+#pragma unroll
+        for (int w = 0; w < W; w++) {
+            num[w] += (double)bn[w];
+            den[w] += (double)bd[w];
         }
         // reduce-scatter over the group's lanes: at offset o the lanes with bit o set
         // keep the upper half of the remaining slots (values first: a conditional of
@@ -949,14 +961,15 @@ __global__ void k_lambda_min(long long n, const double *__restrict__ degG, const
     }
 }
 
-// ------------------------------------------------------------ FP64 refinement
-// r = b - L_P x in FP64 (difference form), grounded at root; r32 = r rounded to T
+// ------------------------------------------------------------ FP64 outer iteration
+// r = b - L_P x in FP64 (difference form), grounded at root; r32 = r rounded to T,
+// r64 (optional) = r
 template <typename T, int KP>
 __global__ __launch_bounds__(kThreads) void k_resid64(long long n, int k, const int *__restrict__ prow,
                                                       const int *__restrict__ pcol, const double *__restrict__ pval,
                                                       const T *__restrict__ b, const double *__restrict__ x,
-                                                      T *__restrict__ r32, int root, double *__restrict__ part,
-                                                      int nblk) {
+                                                      T *__restrict__ r32, double *__restrict__ r64, int root,
+                                                      double *__restrict__ part, int nblk) {
     constexpr int G = kThreads / KP;
     constexpr int RPB = G * kRowsPerGroup;
     __shared__ double sh[G][KP];
@@ -975,6 +988,7 @@ __global__ __launch_bounds__(kThreads) void k_resid64(long long n, int k, const 
             for (int p = prow[v]; p < pe; p++) lx += pval[p] * (xv - x[(long long)pcol[p] * k + j]);
             double rv = (v == root) ? 0.0 : (double)b[v * k + j] - lx;
             r32[v * k + j] = (T)rv;
+            if (r64) r64[v * k + j] = rv;
             acc2 += rv * rv;
         }
     }
@@ -984,6 +998,153 @@ __global__ __launch_bounds__(kThreads) void k_resid64(long long n, int k, const 
         double t = 0.0;
         for (int q = 0; q < G; q++) t += sh[q][j];
         part[(long long)bid * KP + j] = t;
+    }
+}
+
+// Flexible CG in FP64 around the working-precision block PCG (one recurrence per
+// column): the block PCG returns z ~ L_P^-1 r; the direction is z made
+// L_P-orthogonal to the previous one, and the step along it minimizes the energy
+// norm of the error, so an inaccurate inner solve slows the iteration but cannot
+// make it diverge. Reductions run over fixed row blocks, summed in index order.
+//
+// w = L_P z in FP64 (z in working precision, difference form, grounded at root);
+// with adp, per-block partials of z'(A d_prev) per column
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_apply64(long long n, int k, const int *__restrict__ prow,
+                                                      const int *__restrict__ pcol, const double *__restrict__ pval,
+                                                      const T *__restrict__ z, double *__restrict__ w,
+                                                      const double *__restrict__ adp, int root,
+                                                      double *__restrict__ part, int nblk) {
+    constexpr int G = kThreads / KP;
+    constexpr int RPB = G * kRowsPerGroup;
+    __shared__ double sh[G][KP];
+    int bid = xcd_block(blockIdx.x, gridDim.x);
+    if (bid >= nblk) return;
+    int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    double acc = 0.0;
+    if (j < k) {
+        long long r0 = (long long)bid * RPB;
+        for (int i = g; i < RPB; i += G) {
+            long long v = r0 + i;
+            if (v >= n) break;
+            const double zv = (double)z[v * k + j];
+            double lz = 0.0;
+            const int pe = prow[v + 1];
+            for (int p = prow[v]; p < pe; p++) lz += pval[p] * (zv - (double)z[(long long)pcol[p] * k + j]);
+            if (v == root) lz = 0.0;
+            w[v * k + j] = lz;
+            if (adp) acc += zv * adp[v * k + j];
+        }
+    }
+    sh[g][j] = acc;
+    __syncthreads();
+    if (g == 0 && adp) {
+        double t = 0.0;
+        for (int q = 0; q < G; q++) t += sh[q][j];
+        part[(long long)bid * KP + j] = t;
+    }
+}
+
+// d = z - beta d, Ad = w - beta Ad (beta per column; first: d = z, Ad = w, the
+// previous direction not read); per-block partials of d'r (offset 0) and d'Ad
+// (offset KP)
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_fcg64_dir(long long n, int k, int first, const double *__restrict__ beta,
+                                                        const T *__restrict__ z, const double *__restrict__ w,
+                                                        const double *__restrict__ r, double *__restrict__ d,
+                                                        double *__restrict__ ad, double *__restrict__ part,
+                                                        int nblk) {
+    constexpr int G = kThreads / KP;
+    constexpr int RPB = G * kRowsPerGroup;
+    __shared__ double s1[G][KP], s2[G][KP];
+    int bid = xcd_block(blockIdx.x, gridDim.x);
+    if (bid >= nblk) return;
+    int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    double dr = 0.0, dad = 0.0;
+    if (j < k) {
+        const double bj = beta[j];
+        long long r0 = (long long)bid * RPB;
+        for (int i = g; i < RPB; i += G) {
+            long long v = r0 + i;
+            if (v >= n) break;
+            const long long o = v * k + j;
+            const double dn = first ? (double)z[o] : (double)z[o] - bj * d[o];
+            const double an = first ? w[o] : w[o] - bj * ad[o];
+            d[o] = dn;
+            ad[o] = an;
+            dr += dn * r[o];
+            dad += dn * an;
+        }
+    }
+    s1[g][j] = dr;
+    s2[g][j] = dad;
+    __syncthreads();
+    if (g == 0) {
+        double a = 0.0, c = 0.0;
+        for (int q = 0; q < G; q++) {
+            a += s1[q][j];
+            c += s2[q][j];
+        }
+        part[(long long)bid * 2 * KP + j] = a;
+        part[(long long)bid * 2 * KP + KP + j] = c;
+    }
+}
+
+// x += alpha d, r -= alpha Ad, r32 = r rounded to T, z = 0 (the inner solve's
+// accumulator, cleared for the next one); per-block partials of r'r
+template <typename T, int KP>
+__global__ __launch_bounds__(kThreads) void k_fcg64_step(long long n, int k, const double *__restrict__ alpha,
+                                                         const double *__restrict__ d, const double *__restrict__ ad,
+                                                         double *__restrict__ x, double *__restrict__ r,
+                                                         T *__restrict__ r32, T *__restrict__ z,
+                                                         double *__restrict__ part, int nblk) {
+    constexpr int G = kThreads / KP;
+    constexpr int RPB = G * kRowsPerGroup;
+    __shared__ double sh[G][KP];
+    int bid = xcd_block(blockIdx.x, gridDim.x);
+    if (bid >= nblk) return;
+    int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    double rr = 0.0;
+    if (j < k) {
+        const double aj = alpha[j];
+        long long r0 = (long long)bid * RPB;
+        for (int i = g; i < RPB; i += G) {
+            long long v = r0 + i;
+            if (v >= n) break;
+            const long long o = v * k + j;
+            x[o] += aj * d[o];
+            const double rn = r[o] - aj * ad[o];
+            r[o] = rn;
+            r32[o] = (T)rn;
+            z[o] = (T)0;
+            rr += rn * rn;
+        }
+    }
+    sh[g][j] = rr;
+    __syncthreads();
+    if (g == 0) {
+        double t = 0.0;
+        for (int q = 0; q < G; q++) t += sh[q][j];
+        part[(long long)bid * KP + j] = t;
+    }
+}
+
+// FCG coefficients per column from reduced dots in red:
+//   FIRST beta = 0; NEXT beta = z'Ad_prev / d_prev'Ad_prev; ALPHA alpha = d'r / d'Ad
+//   (0 when d'Ad <= 0: a direction without energy adds nothing), d_prev'Ad_prev = d'Ad
+enum : int { FC64_FIRST = 0, FC64_NEXT = 1, FC64_ALPHA = 2 };
+__global__ void k_fcg64_coef(int k, int op, double *__restrict__ red) {
+    const int j = threadIdx.x;
+    if (j >= k) return;
+    if (op == FC64_FIRST) {
+        red[RED_FB * kMaxK + j] = 0.0;
+    } else if (op == FC64_NEXT) {
+        const double p = red[RED_DADP * kMaxK + j];
+        red[RED_FB * kMaxK + j] = p > 0.0 ? red[RED_ZAD * kMaxK + j] / p : 0.0;
+    } else {
+        const double dad = red[RED_DAD * kMaxK + j];
+        red[RED_FA * kMaxK + j] = dad > 0.0 ? red[RED_DR * kMaxK + j] / dad : 0.0;
+        red[RED_DADP * kMaxK + j] = dad;
     }
 }
 
@@ -1011,16 +1172,6 @@ __global__ __launch_bounds__(kThreads) void k_norm2(long long n, int k, const T 
         double t = 0.0;
         for (int q = 0; q < G; q++) t += sh[q][j];
         part[(long long)blockIdx.x * KP + j] = t;
-    }
-}
-
-// x64 += dx; dx = 0 (the correction accumulated in working precision moves into
-// the FP64 solution)
-template <typename T>
-__global__ void k_fold_dx(long long nk, double *__restrict__ x64, T *__restrict__ dx) {
-    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (long long)gridDim.x * blockDim.x) {
-        x64[i] += (double)dx[i];
-        dx[i] = (T)0;
     }
 }
 
@@ -1083,7 +1234,7 @@ static int lap_blocks(const Dims &d) { return div_up(d.n, lap_rows_per_block(d.k
 static int score_epr(const Dims &d) {
     const int W = d.prec == 64 ? 2 : 4;
     if (d.k != d.kp || d.kp < W) return kThreads;
-    return (kThreads / (d.kp / W)) * 8;
+    return (kThreads / (d.kp / W)) * scorev_sb(d.kp / W);
 }
 static int score_rounds(const Dims &d) { return div_up(div_up(d.m, score_epr(d)), kScoreBlocksMax); }
 static int score_blocks(const Dims &d) { return div_up(div_up(d.m, score_epr(d)), score_rounds(d)); }
@@ -1121,7 +1272,10 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
     v.q = a.take<T>(nk);
     v.dx = a.take<T>(nk);
     v.x64 = a.take<double>(nk);
-    v.r64 = nullptr;
+    v.r64 = a.take<double>(nk);
+    v.d64 = a.take<double>(nk);
+    v.ad64 = a.take<double>(nk);
+    v.w64 = a.take<double>(nk);
     long long parts = std::max<long long>({(long long)lap_blocks(d) + 8, (long long)vec_blocks(d) + 8, d.ntiles, 2ll * score_blocks(d),
                                            (long long)gauss_blocks(d)});
     v.part = a.take<double>(parts * d.kp + 64);
@@ -1161,6 +1315,24 @@ void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, co
     GR_CHECK_LAUNCH();
 }
 
+// y = L x with padded rows of width E: the 16-byte-lane kernel for rows of whole
+// 16-byte slices (k a power of two), else the one-value-per-lane kernel
+template <typename T, int KP, int E>
+static void lap_launch(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x,
+                       T *y, int root, const unsigned long long *scale_from, double *dot_part, int nb, hipStream_t s) {
+    if constexpr (lapv_ok<T, KP>()) {
+        if (d.k == KP && dot_part == nullptr) {
+            constexpr int RPB = 4 * (64 / (KP / V16<T>::W));
+            const int nv = div_up(d.n, RPB);
+            hipLaunchKernelGGL((k_lapv<T, KP, E, kLapNTStore>), dim3(xcd_grid(nv)), dim3(256), 0, s, d.n, rowptr, col,
+                               val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, nv);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_lap<T, KP, E>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr, col, val,
+                       ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
+}
+
 template <typename T>
 void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x, T *y,
                int root, const unsigned long long *scale_from, double *dot_part, hipStream_t s) {
@@ -1171,30 +1343,10 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
                  s);
     lap_long<T>(d, rowptr, col, val, ell, x, s);
     KP_DISPATCH(d.kp, {
-        bool done = false;
-        if constexpr (lapv_ok<T, KP>()) {
-            // rows of whole 16-byte slices (k a power of two): the vector-lane kernel
-            if (d.k == KP && dot_part == nullptr) {
-                constexpr int RPB = 4 * (64 / (KP / V16<T>::W));
-                const int nv = div_up(d.n, RPB);
-                if (ell.E == kEllP)
-                    hipLaunchKernelGGL((k_lapv<T, KP, kEllP, kLapNTStore>), dim3(xcd_grid(nv)), dim3(256), 0, s, d.n,
-                                       rowptr, col, val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from,
-                                       nv);
-                else
-                    hipLaunchKernelGGL((k_lapv<T, KP, kEllG, kLapNTStore>), dim3(xcd_grid(nv)), dim3(256), 0, s, d.n,
-                                       rowptr, col, val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from,
-                                       nv);
-                done = true;
-            }
-        }
-        if (!done) {
-            if (ell.E == kEllP)
-                hipLaunchKernelGGL((k_lap<T, KP, kEllP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr,
-                                   col, val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
-            else
-                hipLaunchKernelGGL((k_lap<T, KP, kEllG>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.n, d.k, rowptr,
-                                   col, val, ell.tail, ell.col, ell.val, ell.deg, x, y, root, scale_from, dot_part, nb);
+        switch (ell.E) {
+        case 4: lap_launch<T, KP, 4>(d, rowptr, col, val, ell, x, y, root, scale_from, dot_part, nb, s); break;
+        case 6: lap_launch<T, KP, 6>(d, rowptr, col, val, ell, x, y, root, scale_from, dot_part, nb, s); break;
+        default: lap_launch<T, KP, 8>(d, rowptr, col, val, ell, x, y, root, scale_from, dot_part, nb, s); break;
         }
     });
     GR_CHECK_LAUNCH();
@@ -1275,24 +1427,11 @@ void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride
     GR_CHECK_LAUNCH();
 }
 
+// max_j ||r_j|| / ||b_j|| from the squared norms in red[RED_RN] and red[RED_BN]
 template <typename T>
-double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, bool fold, hipStream_t s) {
-    const long long nk = d.n * d.k;
-    const int nbv = vec_blocks(d);
-    if (fold) {
-        hipLaunchKernelGGL(k_fold_dx<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, v.dx);
-        GR_CHECK_LAUNCH();
-    }
-    {
-        ProfScope ps(PK_RESID64, 4.0 * (d.n + 1) + 12.0 * d.p_nnz + (double)d.n * d.k * (8 + 2 * sizeof(T)), s);
-        KP_DISPATCH(d.kp, {
-            hipLaunchKernelGGL((k_resid64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol,
-                               t.pval64, b, v.x64, v.r, 0, v.part, nbv);
-        });
-    }
-    GR_CHECK_LAUNCH();
-    double *bn = v.red + RED_BN * kMaxK, *rn = v.red + RED_RN * kMaxK;
-    col_sum<T>(d, v, v.part, nbv, d.kp, 0, rn, s);
+static double worst_rel_resid(Vecs<T> &v, const Dims &d, hipStream_t s) {
+    static_assert(RED_RN == RED_BN + 1, "norms of b and r are read together");
+    double *bn = v.red + RED_BN * kMaxK;
     std::vector<double> hb(2 * kMaxK);
     GR_HIP(hipMemcpyAsync(hb.data(), bn, 2 * kMaxK * sizeof(double), hipMemcpyDeviceToHost, s));
     GR_HIP(hipStreamSynchronize(s));
@@ -1305,6 +1444,53 @@ double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, bool fold, 
         worst = rel > worst ? rel : worst;
     }
     return worst;
+}
+
+template <typename T>
+double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, hipStream_t s) {
+    const int nbv = vec_blocks(d);
+    {
+        ProfScope ps(PK_RESID64, 4.0 * (d.n + 1) + 12.0 * d.p_nnz + (double)d.n * d.k * (16 + 2 * sizeof(T)), s);
+        KP_DISPATCH(d.kp, {
+            hipLaunchKernelGGL((k_resid64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol,
+                               t.pval64, b, v.x64, v.r, v.r64, 0, v.part, nbv);
+        });
+    }
+    GR_CHECK_LAUNCH();
+    col_sum<T>(d, v, v.part, nbv, d.kp, 0, v.red + RED_RN * kMaxK, s);
+    return worst_rel_resid(v, d, s);
+}
+
+template <typename T>
+double fcg_outer_step(Topo &t, Vecs<T> &v, const Dims &d, bool first, hipStream_t s) {
+    const int nbv = vec_blocks(d);
+    double *red = v.red;
+    {
+        ProfScope ps(PK_RESID64, 4.0 * (d.n + 1) + 12.0 * d.p_nnz + (double)d.n * d.k * (sizeof(T) + 56), s);
+        KP_DISPATCH(d.kp, {
+            // w = A z (with z'Ad_prev after the first step)
+            hipLaunchKernelGGL((k_apply64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow,
+                               t.pcol, t.pval64, v.dx, v.w64, first ? (const double *)nullptr : v.ad64, 0, v.part,
+                               nbv);
+            GR_CHECK_LAUNCH();
+            if (!first) col_sum<T>(d, v, v.part, nbv, KP, 0, red + RED_ZAD * kMaxK, s);
+            hipLaunchKernelGGL(k_fcg64_coef, dim3(1), dim3(kMaxK), 0, s, d.k, first ? (int)FC64_FIRST : (int)FC64_NEXT,
+                               red);
+            // d = z - beta d, Ad = w - beta Ad; d'r, d'Ad; alpha
+            hipLaunchKernelGGL((k_fcg64_dir<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, (int)first,
+                               red + RED_FB * kMaxK, v.dx, v.w64, v.r64, v.d64, v.ad64, v.part, nbv);
+            GR_CHECK_LAUNCH();
+            col_sum<T>(d, v, v.part, nbv, 2 * KP, 0, red + RED_DR * kMaxK, s);
+            col_sum<T>(d, v, v.part, nbv, 2 * KP, KP, red + RED_DAD * kMaxK, s);
+            hipLaunchKernelGGL(k_fcg64_coef, dim3(1), dim3(kMaxK), 0, s, d.k, (int)FC64_ALPHA, red);
+            // x += alpha d, r -= alpha Ad, r32 = r, z = 0; r'r
+            hipLaunchKernelGGL((k_fcg64_step<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k,
+                               red + RED_FA * kMaxK, v.d64, v.ad64, v.x64, v.r64, v.r, v.dx, v.part, nbv);
+            GR_CHECK_LAUNCH();
+            col_sum<T>(d, v, v.part, nbv, KP, 0, red + RED_RN * kMaxK, s);
+        });
+    }
+    return worst_rel_resid(v, d, s);
 }
 
 template <typename T>
@@ -1327,7 +1513,7 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     // a target looser than the inner phase's reduction ends that phase at the target
     pp.itol = std::max(pp.itol, pp.rtol);
     pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
-    pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 20;
+    pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 50;
     SolveInfo info = block_pcg<T>(t, v, d, b, pp, s);
     fill_u32(reinterpret_cast<unsigned *>(v.u64s + U_ABSMAX), 2, 0u, s);
     hipLaunchKernelGGL(k_x64_out<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, x, v.u64s + U_ABSMAX);
@@ -1345,8 +1531,14 @@ void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStr
         if constexpr (lapv_ok<T, KP>()) {
             if (d.k == KP) {
                 if (ScoreV<T, KP>::EPR != score_epr(d)) throw Error(GRASS_ERR_DEVICE, "scorer round size mismatch");
-                hipLaunchKernelGGL((k_scorev<T, KP>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m, score_rounds(d),
-                                   nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part, v.u64s + U_HMAX, t.devflags);
+                if ((unsigned long long)d.n * d.k * sizeof(T) < (1ull << 32))
+                    hipLaunchKernelGGL((k_scorev<T, KP, false>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m,
+                                       score_rounds(d), nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part,
+                                       v.u64s + U_HMAX, t.devflags);
+                else
+                    hipLaunchKernelGGL((k_scorev<T, KP, true>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m,
+                                       score_rounds(d), nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part,
+                                       v.u64s + U_HMAX, t.devflags);
                 vec = true;
             }
         }
@@ -1398,7 +1590,8 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
     template void tree_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const T *, double *,            \
                                 unsigned long long *, hipStream_t, const T *, double *, int *, double *,         \
                                 const double *, T *);                                                            \
-    template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, bool, hipStream_t);            \
+    template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, hipStream_t);                  \
+    template double fcg_outer_step<T>(Topo &, Vecs<T> &, const Dims &, bool, hipStream_t);                      \
     template SolveInfo pcg_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const grass_opts &,         \
                                     hipStream_t);                                                                \
     template void score_edges<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, hipStream_t);                  \

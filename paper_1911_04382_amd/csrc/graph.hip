@@ -597,6 +597,40 @@ __global__ void k_ell_fill(long long n, int E, const int *__restrict__ rowptr, c
         }
     }
 }
+// rows longer than 4 and longer than 6 entries
+__global__ void k_count_long(long long n, const int *__restrict__ rowptr, int *__restrict__ cnt) {
+    int c4 = 0, c6 = 0;
+    GSTRIDE(v, n) {
+        const int d = rowptr[v + 1] - rowptr[v];
+        c4 += d > 4;
+        c6 += d > 6;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        c4 += __shfl_xor(c4, off, 64);
+        c6 += __shfl_xor(c6, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (c4) atomicAdd(&cnt[0], c4);
+        if (c6) atomicAdd(&cnt[1], c6);
+    }
+}
+
+// Padded width of the rows of L_G: the narrowest of 4, 6, 8 entries that holds
+// whole rows for all but 1% of them (the rest continue in the CSR). A product
+// gathers E rows per row whatever its length, so padding costs bandwidth: the
+// 100^3 mesh (at most 6 neighbours) takes 6, the grid with long-range edges 6.
+int choose_ell_width(long long n, const int *rowptr, int *cnt, hipStream_t s) {
+    fill_i32(cnt, 2, 0, s);
+    hipLaunchKernelGGL(k_count_long, dim3(grid_for(n)), dim3(256), 0, s, n, rowptr, cnt);
+    GR_CHECK_LAUNCH();
+    int h[2] = {0, 0};
+    GR_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    GR_HIP(hipStreamSynchronize(s));
+    if (h[0] * 100ll <= n) return 4;
+    if (h[1] * 100ll <= n) return 6;
+    return 8;
+}
+
 template <typename T>
 void fill_ell(long long n, const int *rowptr, const int *col, const T *val, Ell<T> &e, hipStream_t s) {
     fill_i32(e.lcount, 1, 0, s);
@@ -635,6 +669,7 @@ void build_csr(Topo &t, Vecs<T> &v, SetupTmp &st, hipStream_t s) {
     GR_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_row_finish<T>, dim3(grid_for(n)), dim3(256), 0, s, n, t.rowptr, t.ceid, t.w, v.cval, t.degG);
     GR_CHECK_LAUNCH();
+    v.eg.E = choose_ell_width(n, t.rowptr, v.eg.lcount, s);  // within the kEllG slots planned
     fill_ell<T>(n, t.rowptr, t.col, v.cval, v.eg, s);
     hipLaunchKernelGGL(k_cast_w<T>, dim3(grid_for(m)), dim3(256), 0, s, m, t.w, v.wT);
     GR_CHECK_LAUNCH();

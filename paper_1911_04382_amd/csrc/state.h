@@ -123,7 +123,8 @@ struct Vecs {
     T *heat = nullptr;    // [m] (internal heat when the caller gives none)
     // PCG
     T *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *dx = nullptr;  // [n*kp]
-    double *x64 = nullptr, *r64 = nullptr;  // [n*kp]
+    // the FP64 outer iteration of the L_P solve: solution, residual, direction, A d, A z
+    double *x64 = nullptr, *r64 = nullptr, *d64 = nullptr, *ad64 = nullptr, *w64 = nullptr;  // [n*k]
     // reductions
     double *part = nullptr;   // [ntiles*kp*2] per-block partials
     double *part2 = nullptr;  // [64*kp] first-stage column sums
