@@ -150,6 +150,24 @@ size_t grass_workspace_bytes(int64_t n, int64_t m, const grass_opts *opts);
 grass_status grass_sparsify(grass_ctx *ctx, const grass_graph *g, const grass_opts *opts, void *workspace,
                             size_t ws_bytes, grass_result *res, void *stream);
 
+/* Bytes of the static device scratch of grass_sparsify_static (one per GPU). */
+#define GRASS_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/* grass_sparsify for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and outputs, with the workspace taken from a static device array of
+ * GRASS_STATIC_SCRATCH_BYTES (256 MiB) that the library holds on each GPU until the
+ * process ends, instead of a caller's buffer. No hipMalloc, hipFree or other
+ * allocating routine is called (nor per-kernel event timing). A graph whose
+ * grass_workspace_bytes exceeds the scratch is rejected with GRASS_ERR_OOM before
+ * any device work (a 3-D mesh of about 110,000 nodes at k = 16, FP32). Every call
+ * on one GPU shares that GPU's scratch, which keeps the last call's contents (each
+ * call initializes what it reads): calls that overlap on one GPU race, so serialize
+ * them (one stream, or host ordering). The scratch is resolved for a device by
+ * grass_create. Inputs and outputs as grass_sparsify. */
+grass_status grass_sparsify_static(grass_ctx *ctx, const grass_graph *g, const grass_opts *opts, grass_result *res,
+                                   void *stream);
+
 /* Many independent graphs in one call (the same method as grass_sparsify, per
  * graph: Sec. IV-D). graphs, opts, results, statuses: host arrays of count entries
  * (the grass_graph entries hold device pointers as for grass_sparsify; opts may

@@ -143,6 +143,9 @@ def load_library(path: str = LIB_PATH):
     L.grass_sparsify.argtypes = [vp, ctypes.POINTER(grass_graph), ctypes.POINTER(grass_opts), vp, ctypes.c_size_t,
                                  ctypes.POINTER(grass_result), vp]
     L.grass_sparsify.restype = st
+    L.grass_sparsify_static.argtypes = [vp, ctypes.POINTER(grass_graph), ctypes.POINTER(grass_opts),
+                                        ctypes.POINTER(grass_result), vp]
+    L.grass_sparsify_static.restype = st
     L.grass_spanning_tree.argtypes = [vp, ctypes.POINTER(grass_graph), vp, vp, ctypes.c_size_t, vp]
     L.grass_spanning_tree.restype = st
     L.grass_low_stretch_tree_workspace_bytes.argtypes = [i64, i64]
@@ -349,6 +352,22 @@ def grass_sparsify(ctx: Context, g: DeviceGraph, opts: grass_opts, ws=None, stre
             part = SparsifyResult(rc, mask, None, summ.as_dict(),
                                   [tr[i].as_dict() for i in range(min(summ.passes, trace_cap))])
         raise GrassError(rc, ctx.last_error(), part)
+    trace = [tr[i].as_dict() for i in range(min(summ.passes, trace_cap))]
+    return SparsifyResult(rc, mask, scores, summ.as_dict(), trace)
+
+
+STATIC_SCRATCH_BYTES = 256 << 20  # GRASS_STATIC_SCRATCH_BYTES of include/grass.h
+
+
+def grass_sparsify_static(ctx: Context, g: DeviceGraph, opts: grass_opts, stream=None, trace_cap=256):
+    """grass_sparsify over the library's static device scratch (no device allocation
+    by the library; the outputs are allocated here, by the caller)."""
+    mask, scores, summ, tr, res = _result_buffers(g, opts, trace_cap)
+    gc = g.c()
+    rc = ctx.lib.grass_sparsify_static(ctx.h, ctypes.byref(gc), ctypes.byref(opts), ctypes.byref(res),
+                                       _stream_ptr(stream))
+    if rc < 0:
+        raise GrassError(rc, ctx.last_error())
     trace = [tr[i].as_dict() for i in range(min(summ.passes, trace_cap))]
     return SparsifyResult(rc, mask, scores, summ.as_dict(), trace)
 

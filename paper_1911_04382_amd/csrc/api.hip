@@ -430,7 +430,7 @@ grass_status select_impl(grass_ctx *ctx, const grass_graph &g, uint8_t *p_mask, 
 }
 
 template <typename F>
-grass_status guarded(grass_ctx *ctx, F f) {
+grass_status guarded(grass_ctx *ctx, F f, bool profile = true) {
     if (!ctx) return GRASS_ERR_INVALID;
     struct Bind {
         Bind(Profiler *p) { g_prof = p; }
@@ -441,7 +441,7 @@ grass_status guarded(grass_ctx *ctx, F f) {
     };
     try {
         GR_HIP(hipSetDevice(ctx->device));
-        Bind bind(&ctx->prof);
+        Bind bind(profile ? &ctx->prof : nullptr);
         grass_status st = f();
         ctx->last_error.clear();
         return st;
@@ -475,6 +475,38 @@ grass_status sparsify_run(grass_ctx *ctx, const grass_graph &g, const grass_opts
 
 using namespace grass;
 
+// The workspace of grass_sparsify_static: a device array of fixed size, one copy per
+// GPU, held until the process ends. Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in for the device symbol); it
+// uses the device address that hipGetSymbolAddress returns for each GPU.
+static __device__ __align__(256) unsigned char scratch[GRASS_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch` on each GPU
+
+// Resolve `scratch` on `device` once (that device current); returns its address.
+void *resolve_scratch(int device) {
+    require(device >= 0 && device < kMaxDevices, GRASS_ERR_DEVICE, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        int prev = 0;
+        GR_HIP(hipGetDevice(&prev));
+        GR_HIP(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        (void)hipSetDevice(prev);
+        if (e != hipSuccess || p == nullptr) {
+            (void)hipGetLastError();
+            throw Error(GRASS_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+}  // namespace
+
 extern "C" {
 
 grass_status grass_create(int device, grass_ctx **out) {
@@ -484,8 +516,15 @@ grass_status grass_create(int device, grass_ctx **out) {
         (void)hipGetLastError();
         return GRASS_ERR_DEVICE;
     }
+    void *sp = nullptr;
+    try {
+        sp = resolve_scratch(device);
+    } catch (const Error &) {
+        return GRASS_ERR_DEVICE;
+    }
     *out = new grass_ctx();
     (*out)->device = device;
+    (*out)->static_ws = sp;
     return GRASS_OK;
 }
 
@@ -535,6 +574,29 @@ grass_status grass_sparsify(grass_ctx *ctx, const grass_graph *g, const grass_op
         if (opts->precision == 64) return sparsify_impl<double>(ctx, *g, *opts, workspace, ws_bytes, res, s);
         return sparsify_impl<float>(ctx, *g, *opts, workspace, ws_bytes, res, s);
     });
+}
+
+grass_status grass_sparsify_static(grass_ctx *ctx, const grass_graph *g, const grass_opts *opts, grass_result *res,
+                                   void *stream) {
+    return guarded(
+        ctx,
+        [&]() -> grass_status {
+            check_graph(g);
+            require(opts && res, GRASS_ERR_INVALID, "opts and result are required");
+            check_opts(*opts);
+            const size_t need = plan_bytes(g->n, g->m, opts->k, opts->precision);
+            require(need <= GRASS_STATIC_SCRATCH_BYTES, GRASS_ERR_OOM,
+                    "the graph needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                        std::to_string((size_t)GRASS_STATIC_SCRATCH_BYTES) +
+                        " of the static scratch: use grass_sparsify with a workspace");
+            require(ctx->static_ws != nullptr, GRASS_ERR_DEVICE, "the static scratch was not resolved");
+            hipStream_t s = static_cast<hipStream_t>(stream);
+            // the same driver and kernels as grass_sparsify, over the static scratch
+            if (opts->precision == 64)
+                return sparsify_impl<double>(ctx, *g, *opts, ctx->static_ws, GRASS_STATIC_SCRATCH_BYTES, res, s);
+            return sparsify_impl<float>(ctx, *g, *opts, ctx->static_ws, GRASS_STATIC_SCRATCH_BYTES, res, s);
+        },
+        /*profile=*/false);  // per-kernel event timing creates events: not on this path
 }
 
 grass_status grass_spanning_tree(grass_ctx *ctx, const grass_graph *g, uint8_t *tree_mask, void *workspace,

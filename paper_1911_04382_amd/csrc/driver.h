@@ -8,6 +8,7 @@
 
 struct grass_ctx {
     int device = 0;
+    void *static_ws = nullptr;  // this device's copy of the library's static scratch (grass_sparsify_static)
     std::string last_error;
     void *own_ws = nullptr;
     size_t own_bytes = 0;
