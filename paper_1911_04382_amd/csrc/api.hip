@@ -4,6 +4,7 @@
 #include <chrono>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "driver.h"
 #include "embed.h"
@@ -177,28 +178,47 @@ PassResult run_pass(Session<T> &S, const grass_opts &o, int pass, bool use_pcg, 
     Vecs<T> &v = S.v;
     PassResult pr;
     T *H = v.H, *Y = v.Y;
-    start_vectors<T>(d, o.seed, pass, H, v, s);
+    if (use_pcg && !std::is_same<T, double>::value) {
+        // passes that solve with L_P keep h0 and every right-hand side L_G h in FP64:
+        // rounding a right-hand side to FP32 adds white noise whose smooth part, which
+        // an ill-conditioned L_P amplifies, outweighs the right-hand side's own
+        Vecs<double> vd;
+        vd.part = v.part;
+        vd.red = v.red;
+        start_vectors<double>(d, o.seed, pass, v.x64, vd, s);
+    } else {
+        start_vectors<T>(d, o.seed, pass, H, v, s);
+    }
     unsigned long long *absmax = v.u64s + U_ABSMAX;
     int steps = o.lambda_steps > o.t ? o.lambda_steps : o.t;
     for (int step = 1; step <= steps; step++) {
-        lap_apply<T>(d, t.rowptr, t.col, v.cval, v.eg, H, Y, -1, step > 1 ? absmax : nullptr, nullptr, s);
+        // after an L_P solve its FP64 solution is at hand (H is it rounded to T): the
+        // next product reads it and keeps the right-hand side in FP64
+        const bool rhs64 = use_pcg && (step > 1 || !std::is_same<T, double>::value);
+        if (rhs64)
+            lap_apply_x64(t, d, v.x64, v.b64, step > 1 ? absmax : nullptr, s);
+        else
+            lap_apply<T>(d, t.rowptr, t.col, v.cval, v.eg, H, Y, -1, step > 1 ? absmax : nullptr, nullptr, s);
         fill_u32(reinterpret_cast<unsigned *>(absmax), 2, 0u, s);
         if (!use_pcg) {
             tree_solve<T>(t, v, d, Y, Y, nullptr, nullptr, absmax, s);
             std::swap(H, Y);
         } else {
-            SolveInfo si = pcg_solve<T>(t, v, d, Y, H, o, s);
+            SolveInfo si = pcg_solve<T>(t, v, d, Y, H, o, s, rhs64 ? v.b64 : nullptr);
             pr.pcg_iters += si.iters;
             pr.resid64 = std::max(pr.resid64, si.resid64);
         }
+        // after an L_P solve the FP64 solution is at hand: the scorer takes its
+        // differences there (in FP32 runs H is that solution rounded to FP32)
+        const double *h64 = use_pcg ? v.x64 : nullptr;
         if (step == o.t) {
-            score_edges<T>(t, v, d, H, heat, s);
+            score_edges<T>(t, v, d, H, heat, s, h64);
             if (steps > o.t)
                 GR_HIP(hipMemcpyAsync(v.u64s + 4, v.u64s + U_HMAX, 8, hipMemcpyDeviceToDevice, s));
         }
     }
     if (steps > o.t) {
-        score_edges<T>(t, v, d, H, (T *)nullptr, s);  // Rayleigh quotient of the continued vectors
+        score_edges<T>(t, v, d, H, (T *)nullptr, s, use_pcg ? v.x64 : nullptr);  // Rayleigh quotient of the continued vectors
         GR_HIP(hipMemcpyAsync(v.u64s + U_HMAX, v.u64s + 4, 8, hipMemcpyDeviceToDevice, s));
     }
     pr.sc = finish_estimates<T>(t, v, d, s);

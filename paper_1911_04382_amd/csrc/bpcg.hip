@@ -843,7 +843,8 @@ static void launch_rowmul(const Dims &d, const T *M, const T *In, const T *C, T 
 }
 
 template <typename T>
-SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s) {
+SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s,
+                    const double *b64) {
     const long long nk = d.n * d.k;
     const int root = 0;
     const int KK = d.kp * d.kp;
@@ -852,7 +853,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     SolveInfo info;
     fill_i32(v.tcnt, bpcg_counters(d), 0, s);
     // r = b - L_P x with x = 0; its norms are the reference of the first inner phase
-    info.resid64 = true_residual<T>(t, v, d, b, s);
+    info.resid64 = true_residual<T>(t, v, d, b, s, b64);
     if (info.resid64 <= pp.rtol) return info;
     // a fresh search block: P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
     auto start_block = [&]() {
@@ -912,7 +913,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
                         // the recurrence's residual drifts from b - L_P x by rounding: check
                         // the recomputed one, and if it misses the target go on from it
                         // with a fresh recurrence (residual replacement)
-                        info.resid64 = true_residual<T>(t, v, d, b, s);
+                        info.resid64 = true_residual<T>(t, v, d, b, s, b64);
                         checked = fresh = true;
                     }
                     if (last || info.resid64 <= pp.rtol || info.outer + 1 >= pp.max_repl) stop = true;
@@ -947,7 +948,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     info.outer++;
     info.iters = it;
     // the reported residual is always the one recomputed from the solution
-    if (!checked) info.resid64 = true_residual<T>(t, v, d, b, s);
+    if (!checked) info.resid64 = true_residual<T>(t, v, d, b, s, b64);
     return info;
 }
 
@@ -972,8 +973,8 @@ template void block_gram<double>(const Dims &, const double *, const double *, d
                                  hipStream_t);
 
 template SolveInfo block_pcg<float>(Topo &, Vecs<float> &, const Dims &, const float *, const PcgParams &,
-                                    hipStream_t);
+                                    hipStream_t, const double *);
 template SolveInfo block_pcg<double>(Topo &, Vecs<double> &, const Dims &, const double *, const PcgParams &,
-                                     hipStream_t);
+                                     hipStream_t, const double *);
 
 }  // namespace grass

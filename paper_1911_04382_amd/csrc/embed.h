@@ -42,6 +42,10 @@ void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, co
 // Q'x (qz_q n x k) from per-tile FP64 partials in qz_part (counters qz_cnt), and the
 // last tile stores the k x k total (row-major, ld kp) at qz_out or, with beta_out,
 // stores beta = -G^-1 Q'x there instead (G^-1 at beta_ginv, both k x k, ld kp).
+// y = L_G x64 (grounded nowhere) in FP64, scaled by the power of two from
+// scale_from: the right-hand side of the next L_P solve, kept in FP64.
+void lap_apply_x64(Topo &t, const Dims &d, const double *x64, double *y, const unsigned long long *scale_from,
+                   hipStream_t s);
 template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s, const T *qz_q = nullptr, double *qz_part = nullptr,
@@ -61,12 +65,13 @@ struct SolveInfo {
     int outer = 0;
 };
 template <typename T>
-SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s);
+SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s,
+                    const double *b64 = nullptr);
 
 // r = b - L_P x64 in FP64 (v.r64, and v.r rounded to T), squared norms in
 // red[RED_RN]; returns max_j ||r_j|| / ||b_j|| (b norms in red[RED_BN]).
 template <typename T>
-double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, hipStream_t s);
+double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, hipStream_t s, const double *b64 = nullptr);
 // One FP64 flexible-CG step of the L_P solve with z = v.dx from the inner block PCG
 // (first: start the recurrence): x64, r64, v.r and the norms in red[RED_RN] are
 // updated, v.dx is cleared; returns max_j ||r_j|| / ||b_j||.
@@ -79,7 +84,8 @@ struct PassScalars {
     double lambda_max = 0, lambda_min = 0, heat_max = 0;
 };
 template <typename T>
-void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStream_t s);
+void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStream_t s,
+                 const double *H64 = nullptr);
 template <typename T>
 PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s);
 
@@ -95,7 +101,8 @@ struct PcgParams {
     int max_it = 2000, max_repl = 50;
 };
 template <typename T>
-SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s);
+SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s,
+                    const double *b64 = nullptr);
 
 // Scratch of the block PCG's in-kernel reductions: doubles of Vecs::gpart and
 // counters of Vecs::tcnt.

@@ -5,6 +5,8 @@
 // 55, 61). None of these steps is a dense contraction: every kernel is bound by
 // HBM traffic (or latency), so the design work is coalescing, fusion and the
 // block -> XCD mapping, not MFMA.
+#include <type_traits>
+
 #include "embed.h"
 #include "gram.h"
 #include "kern.h"
@@ -795,15 +797,18 @@ struct ScoreV {
     static constexpr int M = LPR < SB ? SB / LPR : 1;              // edges ending in one lane
     static constexpr int EPR = G * SB;                              // edges per block round
 };
-template <typename T, int KP, bool WIDE>
+// TH: the type of the potentials read (T, or double for the FP64 solution of an L_P
+// solve: each difference h_p - h_q is then taken in FP64 and rounded to T once,
+// instead of differencing two rounded potentials); the geometry follows TH.
+template <typename T, typename TH, int KP, bool WIDE>
 __global__ __launch_bounds__(kThreads) void k_scorev(long long m, int rounds, int nblk, const int *__restrict__ src,
                                                      const int *__restrict__ dst, const T *__restrict__ wT,
-                                                     const uint8_t *__restrict__ mask, const T *__restrict__ H,
+                                                     const uint8_t *__restrict__ mask, const TH *__restrict__ H,
                                                      T *__restrict__ heat, double *__restrict__ part,
                                                      unsigned long long *__restrict__ hmax,
                                                      unsigned *__restrict__ devflags) {
-    using S = ScoreV<T, KP>;
-    using V = typename V16<T>::type;
+    using S = ScoreV<TH, KP>;
+    using V = typename V16<TH>::type;
     constexpr int W = S::W, LPR = S::LPR, SB = S::SB, G = S::G, RUN = S::RUN, M = S::M;
     __shared__ int s_p[G][SB], s_q[G][SB];
     __shared__ T s_w[G][SB], s_wp[G][SB];  // weight; weight if the edge is in P, else 0
@@ -846,16 +851,21 @@ __global__ __launch_bounds__(kThreads) void k_scorev(long long m, int rounds, in
             }
         }
         T sq[SB];
-        V bn = (T)0, bd = (T)0;  // the batch's terms per column, added to the FP64 sums once
+        T bn[W], bd[W];  // the batch's terms per column, added to the FP64 sums once
+#pragma unroll
+        for (int w = 0; w < W; w++) bn[w] = bd[w] = (T)0;
 #pragma unroll
         for (int i = 0; i < SB; i++) {
             const V dv = hp[i] - hq[i];
-            const V d2 = dv * dv;
-            bn += s_w[g][i] * d2;
-            bd += s_wp[g][i] * d2;  // + 0 off P: the same sum
             T acc = (T)0;
 #pragma unroll
-            for (int w = 0; w < W; w++) acc += d2[w];
+            for (int w = 0; w < W; w++) {
+                const T dw = (T)dv[w];
+                const T d2 = dw * dw;
+                bn[w] += s_w[g][i] * d2;
+                bd[w] += s_wp[g][i] * d2;  // + 0 off P: the same sum
+                acc += d2;
+            }
             sq[i] = acc;
         }
 #pragma unroll
@@ -964,10 +974,10 @@ __global__ void k_lambda_min(long long n, const double *__restrict__ degG, const
 // ------------------------------------------------------------ FP64 outer iteration
 // r = b - L_P x in FP64 (difference form), grounded at root; r32 = r rounded to T,
 // r64 (optional) = r
-template <typename T, int KP>
+template <typename T, int KP, typename TB>
 __global__ __launch_bounds__(kThreads) void k_resid64(long long n, int k, const int *__restrict__ prow,
                                                       const int *__restrict__ pcol, const double *__restrict__ pval,
-                                                      const T *__restrict__ b, const double *__restrict__ x,
+                                                      const TB *__restrict__ b, const double *__restrict__ x,
                                                       T *__restrict__ r32, double *__restrict__ r64, int root,
                                                       double *__restrict__ part, int nblk) {
     constexpr int G = kThreads / KP;
@@ -998,6 +1008,36 @@ __global__ __launch_bounds__(kThreads) void k_resid64(long long n, int k, const 
         double t = 0.0;
         for (int q = 0; q < G; q++) t += sh[q][j];
         part[(long long)bid * KP + j] = t;
+    }
+}
+
+// y = L_G x for x the FP64 solution of the previous step's L_P solve: differences
+// and sums in FP64 with the FP64 edge weights, y rounded to T once and scaled by sc
+// (a power of two). Differencing two FP32-rounded potentials of a smooth vector
+// loses the digits that tell them apart; this product keeps them.
+template <typename TY, int KP>
+__global__ __launch_bounds__(kThreads) void k_lap_x64(long long n, int k, const int *__restrict__ rowptr,
+                                                      const int *__restrict__ col, const int *__restrict__ ceid,
+                                                      const double *__restrict__ w, const double *__restrict__ x,
+                                                      TY *__restrict__ y,
+                                                      const unsigned long long *__restrict__ scale_from,
+                                                      int nblk) {
+    constexpr int G = kThreads / KP;
+    constexpr int RPB = G * kRowsPerGroup;
+    int bid = xcd_block(blockIdx.x, gridDim.x);
+    if (bid >= nblk) return;
+    int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    if (j >= k) return;
+    const double sc = pow2_scale(scale_from);
+    long long r0 = (long long)bid * RPB;
+    for (int i = g; i < RPB; i += G) {
+        long long v = r0 + i;
+        if (v >= n) break;
+        const double xv = x[v * k + j];
+        double acc = 0.0;
+        const int pe = rowptr[v + 1];
+        for (int p = rowptr[v]; p < pe; p++) acc += w[ceid[p]] * (xv - x[(long long)col[p] * k + j]);
+        y[v * k + j] = (TY)(acc * sc);
     }
 }
 
@@ -1230,14 +1270,19 @@ static int lap_blocks(const Dims &d) { return div_up(d.n, lap_rows_per_block(d.k
 
 // a round of a scoring block is kThreads consecutive edges (KP per lane group)
 // edges per block round: kThreads for the scalar scorer, ScoreV::EPR for the
-// 16-byte-lane one (used when k is a power of two of at least 16 bytes)
-static int score_epr(const Dims &d) {
-    const int W = d.prec == 64 ? 2 : 4;
+// 16-byte-lane one (used when k is a power of two of at least 16 bytes); h64: the
+// potentials read are FP64
+static int score_epr(const Dims &d, bool h64 = false) {
+    const int W = d.prec == 64 || h64 ? 2 : 4;
     if (d.k != d.kp || d.kp < W) return kThreads;
     return (kThreads / (d.kp / W)) * scorev_sb(d.kp / W);
 }
-static int score_rounds(const Dims &d) { return div_up(div_up(d.m, score_epr(d)), kScoreBlocksMax); }
-static int score_blocks(const Dims &d) { return div_up(div_up(d.m, score_epr(d)), score_rounds(d)); }
+static int score_rounds(const Dims &d, bool h64 = false) {
+    return div_up(div_up(d.m, score_epr(d, h64)), kScoreBlocksMax);
+}
+static int score_blocks(const Dims &d, bool h64 = false) {
+    return div_up(div_up(d.m, score_epr(d, h64)), score_rounds(d, h64));
+}
 static int gauss_blocks(const Dims &d) {
     return (int)std::min<long long>(kGaussBlocksMax, div_up(d.n, kThreads / d.kp));
 }
@@ -1276,7 +1321,8 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
     v.d64 = a.take<double>(nk);
     v.ad64 = a.take<double>(nk);
     v.w64 = a.take<double>(nk);
-    long long parts = std::max<long long>({(long long)lap_blocks(d) + 8, (long long)vec_blocks(d) + 8, d.ntiles, 2ll * score_blocks(d),
+    v.b64 = a.take<double>(nk);
+    long long parts = std::max<long long>({(long long)lap_blocks(d) + 8, (long long)vec_blocks(d) + 8, d.ntiles, 2ll * std::max(score_blocks(d), score_blocks(d, true)),
                                            (long long)gauss_blocks(d)});
     v.part = a.take<double>(parts * d.kp + 64);
     v.part2 = a.take<double>(64 * d.kp + 64);
@@ -1348,6 +1394,17 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
         case 6: lap_launch<T, KP, 6>(d, rowptr, col, val, ell, x, y, root, scale_from, dot_part, nb, s); break;
         default: lap_launch<T, KP, 8>(d, rowptr, col, val, ell, x, y, root, scale_from, dot_part, nb, s); break;
         }
+    });
+    GR_CHECK_LAUNCH();
+}
+
+void lap_apply_x64(Topo &t, const Dims &d, const double *x64, double *y, const unsigned long long *scale_from,
+                   hipStream_t s) {
+    const int nbv = vec_blocks(d);
+    ProfScope ps(PK_SPMM_G, 4.0 * (d.n + 1) + 2.0 * d.m * 16 + (double)d.n * d.k * 16, s);
+    KP_DISPATCH(d.kp, {
+        hipLaunchKernelGGL((k_lap_x64<double, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.rowptr,
+                           t.col, t.ceid, t.w, x64, y, scale_from, nbv);
     });
     GR_CHECK_LAUNCH();
 }
@@ -1447,13 +1504,17 @@ static double worst_rel_resid(Vecs<T> &v, const Dims &d, hipStream_t s) {
 }
 
 template <typename T>
-double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, hipStream_t s) {
+double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, hipStream_t s, const double *b64) {
     const int nbv = vec_blocks(d);
     {
         ProfScope ps(PK_RESID64, 4.0 * (d.n + 1) + 12.0 * d.p_nnz + (double)d.n * d.k * (16 + 2 * sizeof(T)), s);
         KP_DISPATCH(d.kp, {
-            hipLaunchKernelGGL((k_resid64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow, t.pcol,
-                               t.pval64, b, v.x64, v.r, v.r64, 0, v.part, nbv);
+            if (b64)
+                hipLaunchKernelGGL((k_resid64<T, KP, double>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k,
+                                   t.prow, t.pcol, t.pval64, b64, v.x64, v.r, v.r64, 0, v.part, nbv);
+            else
+                hipLaunchKernelGGL((k_resid64<T, KP, T>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow,
+                                   t.pcol, t.pval64, b, v.x64, v.r, v.r64, 0, v.part, nbv);
         });
     }
     GR_CHECK_LAUNCH();
@@ -1494,14 +1555,18 @@ double fcg_outer_step(Topo &t, Vecs<T> &v, const Dims &d, bool first, hipStream_
 }
 
 template <typename T>
-SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s) {
+SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s,
+                    const double *b64) {
     const long long nk = d.n * d.k;
     const int root = 0;
     const int nbv = vec_blocks(d);
     double *bn = v.red + RED_BN * kMaxK;
     // ||b|| per vector (grounded rows)
     KP_DISPATCH(d.kp, {
-        hipLaunchKernelGGL((k_norm2<T, KP>), dim3(nbv), dim3(kThreads), 0, s, d.n, d.k, b, root, v.part);
+        if (b64)
+            hipLaunchKernelGGL((k_norm2<double, KP>), dim3(nbv), dim3(kThreads), 0, s, d.n, d.k, b64, root, v.part);
+        else
+            hipLaunchKernelGGL((k_norm2<T, KP>), dim3(nbv), dim3(kThreads), 0, s, d.n, d.k, b, root, v.part);
     });
     GR_CHECK_LAUNCH();
     col_sum<T>(d, v, v.part, nbv, d.kp, 0, bn, s);
@@ -1514,34 +1579,41 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     pp.itol = std::max(pp.itol, pp.rtol);
     pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
     pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 50;
-    SolveInfo info = block_pcg<T>(t, v, d, b, pp, s);
+    SolveInfo info = block_pcg<T>(t, v, d, b, pp, s, b64);
     fill_u32(reinterpret_cast<unsigned *>(v.u64s + U_ABSMAX), 2, 0u, s);
     hipLaunchKernelGGL(k_x64_out<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, x, v.u64s + U_ABSMAX);
     GR_CHECK_LAUNCH();
     return info;
 }
 
+template <typename T, typename TH, int KP>
+static bool launch_scorev(Topo &t, Vecs<T> &v, const Dims &d, const TH *H, T *heat, int nb, hipStream_t s) {
+    if constexpr (lapv_ok<TH, KP>()) {
+        constexpr bool h64 = !std::is_same<T, TH>::value;
+        if (d.k != KP) return false;
+        if (ScoreV<TH, KP>::EPR != score_epr(d, h64)) throw Error(GRASS_ERR_DEVICE, "scorer round size mismatch");
+        if ((unsigned long long)d.n * d.k * sizeof(TH) < (1ull << 32))
+            hipLaunchKernelGGL((k_scorev<T, TH, KP, false>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m,
+                               score_rounds(d, h64), nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part,
+                               v.u64s + U_HMAX, t.devflags);
+        else
+            hipLaunchKernelGGL((k_scorev<T, TH, KP, true>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m,
+                               score_rounds(d, h64), nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part,
+                               v.u64s + U_HMAX, t.devflags);
+        return true;
+    }
+    return false;
+}
+
 template <typename T>
-void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStream_t s) {
-    int nb = score_blocks(d);
+void score_edges(Topo &t, Vecs<T> &v, const Dims &d, const T *H, T *heat, hipStream_t s, const double *H64) {
+    const bool h64 = H64 != nullptr && !std::is_same<T, double>::value && d.k == d.kp && d.kp >= 2;
+    int nb = score_blocks(d, h64);
     fill_u32(reinterpret_cast<unsigned *>(v.u64s + U_HMAX), 2, 0u, s);
-    ProfScope ps(PK_SCORE, (double)d.m * (9 + 2 * sizeof(T)) + (double)d.n * d.k * sizeof(T), s);
+    ProfScope ps(PK_SCORE, (double)d.m * (9 + 2 * sizeof(T)) + (double)d.n * d.k * (h64 ? 8 : sizeof(T)), s);
     KP_DISPATCH(d.kp, {
-        bool vec = false;
-        if constexpr (lapv_ok<T, KP>()) {
-            if (d.k == KP) {
-                if (ScoreV<T, KP>::EPR != score_epr(d)) throw Error(GRASS_ERR_DEVICE, "scorer round size mismatch");
-                if ((unsigned long long)d.n * d.k * sizeof(T) < (1ull << 32))
-                    hipLaunchKernelGGL((k_scorev<T, KP, false>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m,
-                                       score_rounds(d), nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part,
-                                       v.u64s + U_HMAX, t.devflags);
-                else
-                    hipLaunchKernelGGL((k_scorev<T, KP, true>), dim3(xcd_grid(nb)), dim3(kThreads), 0, s, d.m,
-                                       score_rounds(d), nb, t.src, t.dst, v.wT, t.mask, H, heat, v.part,
-                                       v.u64s + U_HMAX, t.devflags);
-                vec = true;
-            }
-        }
+        bool vec = h64 ? launch_scorev<T, double, KP>(t, v, d, H64, heat, nb, s)
+                       : launch_scorev<T, T, KP>(t, v, d, H, heat, nb, s);
         // 32-bit gather offsets while the n x k block is under 4 GiB
         if (vec) {
         } else if ((unsigned long long)d.n * d.k * sizeof(T) < (1ull << 32))
@@ -1590,11 +1662,11 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
     template void tree_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const T *, double *,            \
                                 unsigned long long *, hipStream_t, const T *, double *, int *, double *,         \
                                 const double *, T *);                                                            \
-    template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, hipStream_t);                  \
+    template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, hipStream_t, const double *);  \
     template double fcg_outer_step<T>(Topo &, Vecs<T> &, const Dims &, bool, hipStream_t);                      \
     template SolveInfo pcg_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const grass_opts &,         \
-                                    hipStream_t);                                                                \
-    template void score_edges<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, hipStream_t);                  \
+                                    hipStream_t, const double *);                                                \
+    template void score_edges<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, hipStream_t, const double *);  \
     template PassScalars finish_estimates<T>(Topo &, Vecs<T> &, const Dims &, hipStream_t);                      \
     template void absmax_of<T>(const Dims &, const T *, unsigned long long *, hipStream_t);               \
     template void col_sum<T>(const Dims &, Vecs<T> &, const double *, int, int, int, double *, hipStream_t);

@@ -77,6 +77,40 @@ def _norm_err(heat, ref, off):
     return np.abs(s - r)[off].max(), s, r
 
 
+REL_FLOOR = 1e-5  # per-edge relative error is checked for oracle scores >= max(cutoff / 2, this)
+
+
+def _cutoff(g, P, ref, sigma2, t, budget_frac=0.01, sim_hops=1, heat=None, stats=None):
+    """The normalized score below which the pass's selection takes no edge: theta of eq.
+    (58), or, when the budget binds first, the score of the last edge the oracle's greedy
+    accepts from the reference scores (Sec. IV-D). The reference is the oracle's pass
+    (ref), or heat and stats given directly."""
+    heat = ref.heat if heat is None else heat
+    stats = ref.stats if stats is None else stats
+    th = O.theta(sigma2, stats["lambda_min"], stats["lambda_max"], t)
+    budget = max(1, int(np.floor(budget_frac * g.n)))
+    Pn, acc, _ = O.filter_select(g, heat, P, th, stats["heat_max"], sim_hops=sim_hops, budget=budget)
+    new = (Pn == 2) & (P == 0)
+    last = (heat[new] / stats["heat_max"]).min() if acc else th
+    return max(th, last)
+
+
+def _fp32_bar(heat, ref, off, theta=0.0, tol=1e-4):
+    """The FP32 bar on normalized scores s = heat / max off-P heat (eq. 58): max |s - s_oracle|
+    <= tol, and per-edge relative error <= tol for every off-P edge whose oracle score is at
+    least max(theta / 2, REL_FLOOR) (below it an edge is far from any cutoff and its heat is a
+    difference of nearly equal FP32 potentials). Returns (max normalized error, max relative
+    error, edges checked)."""
+    err, s, r = _norm_err(heat, ref, off)
+    big = off & (r >= max(theta / 2, REL_FLOOR))
+    rel = float((np.abs(s[big] - r[big]) / r[big]).max()) if big.any() else 0.0
+    say(f"  normalized score error {err:.3e}; per-edge relative error {rel:.3e} over {int(big.sum())} edges "
+        f"(scores >= {max(theta / 2, REL_FLOOR):.1e})")
+    assert err <= tol
+    assert rel <= tol
+    return err, rel, int(big.sum())
+
+
 EMBED_CASES = [
     ("c1_fp64", lambda: G.config_c1(), 8, 2, 64),
     ("c1_fp32", lambda: G.config_c1(), 8, 2, 32),
@@ -107,10 +141,12 @@ def test_embed_tree_pass(ctx, case):
     heat = heat.cpu().numpy().astype(np.float64)
     ref = O.embed(g, tmask, k=k, t=t, seed=11, pass_=2)
     off = tmask == 0
-    err, s, r = _norm_err(heat, ref.heat, off)
-    tol = 1e-10 if prec == 64 else 1e-4
-    say(f"  max normalized score error {err:.3e}; lambda_max {st['lambda_max']:.6g} vs {ref.stats['lambda_max']:.6g}")
-    assert err <= tol
+    say(f"  lambda_max {st['lambda_max']:.6g} vs {ref.stats['lambda_max']:.6g}")
+    if prec == 64:
+        err, s, r = _norm_err(heat, ref.heat, off)
+        assert err <= 1e-10
+    else:
+        _fp32_bar(heat, ref.heat, off, _cutoff(g, tmask, ref, 100.0, t))
     assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-10 if prec == 64 else 1e-4)
     assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
     assert st["m_off"] == off.sum()
@@ -148,10 +184,13 @@ def test_embed_with_added_edges_pcg(ctx, case):
     heat = heat.cpu().numpy().astype(np.float64)
     ref = O.embed(g, P, k=k, t=2, seed=0, pass_=1)
     off = P == 0
-    err, s, r = _norm_err(heat, ref.heat, off)
-    say(f"  pcg iters {st['pcg_iters']}, resid64 {st['pcg_resid64']:.2e}, max score err {err:.3e}")
+    say(f"  pcg iters {st['pcg_iters']}, resid64 {st['pcg_resid64']:.2e}")
     assert st["pcg_resid64"] <= opts.pcg_rtol
-    assert err <= (1e-10 if prec == 64 else 1e-4)
+    if prec == 64:
+        err, s, r = _norm_err(heat, ref.heat, off)
+        assert err <= 1e-10
+    else:
+        _fp32_bar(heat, ref.heat, off, _cutoff(g, P, ref, 100.0, 2))
     assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
     assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
 
@@ -195,26 +234,126 @@ def test_sparsify_c1_fp64_one_pass(ctx):
     assert res.status == ref.status
 
 
-@pytest.mark.parametrize("case", ["grid", "mesh"])
-def test_sparsify_iterative_fp32(ctx, case):
-    if case == "grid":
-        g, k = G.grid2d(32, 32, seed=2), 8
-    else:
-        g, k = G.mesh3d(12, 12, 12, weights=(G.W_LOGUNIFORM10, -3, 3), seed=0), 16
-    say("sparsify iterative FP32:", g.name)
+def _order(cands, score):
+    """Candidates in rank order (score desc, id asc; Sec. III-I step 4)."""
+    return cands[np.lexsort((cands, -score[cands]))]
+
+
+def _check_selection(P, P_gpu, P_ora, s_gpu, s_ora, th_gpu, th_ora, tol=1e-4):
+    """The FP32 selection bar: candidacy (eq. 58) may differ only for edges within tol of
+    the threshold; walking both greedy orders (Sec. IV-D), the first point where they part
+    must be a swap of candidates whose oracle scores are within tol, or an edge within tol
+    of the threshold; choices after it may cascade. Returns the number of differing edges."""
+    off = P == 0
+    c_gpu = np.flatnonzero(off & (s_gpu >= th_gpu))
+    c_ora = np.flatnonzero(off & (s_ora >= th_ora))
+    for e in np.setxor1d(c_gpu, c_ora):
+        assert abs(s_ora[e] - th_ora) <= tol, ("candidacy differs away from the threshold", e, s_ora[e], th_ora)
+    a_gpu = set(np.flatnonzero((P_gpu == 2) & off).tolist())
+    a_ora = set(np.flatnonzero((P_ora == 2) & off).tolist())
+    if a_gpu == a_ora:
+        return 0
+    o_gpu, o_ora = _order(c_gpu, s_gpu), _order(c_ora, s_ora)
+    for i in range(max(len(o_gpu), len(o_ora))):
+        eg = int(o_gpu[i]) if i < len(o_gpu) else None
+        eo = int(o_ora[i]) if i < len(o_ora) else None
+        if eg == eo and (eg in a_gpu) == (eo in a_ora):
+            continue
+        near = [e for e in (eg, eo) if e is not None and abs(s_ora[e] - th_ora) <= tol]
+        tie = eg is not None and eo is not None and abs(s_ora[eg] - s_ora[eo]) <= tol
+        say(f"  selections part at rank {i}: gpu edge {eg} / oracle edge {eo} (tie {tie}, near threshold {near})")
+        assert tie or near, ("the greedy walks part away from a near tie", i, eg, eo)
+        break
+    return len(a_gpu ^ a_ora)
+
+
+LOCKSTEP_CASES = [
+    ("grid_k8_sigma20", lambda: G.grid2d(40, 40, seed=2), 8, 20.0),
+    ("mesh_k16", lambda: G.mesh3d(16, 16, 16, weights=(G.W_LOGUNIFORM10, -3, 3), seed=0), 16, 100.0),
+    # k = 32: the benchmark's fused MFMA block-PCG kernels
+    ("mesh_k32", lambda: G.mesh3d(20, 18, 16, weights=(G.W_LOGUNIFORM10, -3, 3), seed=3), 32, 100.0),
+]
+
+
+@pytest.mark.parametrize("case", LOCKSTEP_CASES, ids=[c[0] for c in LOCKSTEP_CASES])
+def test_lockstep_sparsify_fp32(ctx, case):
+    """FP32 iterative densification in lockstep with the oracle (Sec. IV-D): at every pass
+    the oracle recomputes the pass from the GPU's subgraph P_i (eqs. 28-35, 55, 61) and its
+    own selection (eq. 58, step 6); scores meet the FP32 bar, the lambda estimates 1e-4 /
+    1e-12, and the selections differ only as _check_selection allows. The GPU's selection
+    equals the oracle's greedy run on the GPU's own scores, bit for bit, and grass_sparsify
+    reproduces the pass-by-pass composition exactly."""
+    name, mk, k, s2 = case
+    g = mk()
+    say("lockstep sparsify FP32:", name, g.n, g.m)
     dg = grass.to_device(g, DEV)
-    opts = grass.make_opts(k=k, t=2, precision=32, seed=0, sigma2=20.0 if case == "grid" else 100.0)
+    P = O.max_spanning_tree(g)
+    assert np.array_equal(grass.grass_spanning_tree(ctx, dg).cpu().numpy(), P)
+    opts = grass.make_opts(k=k, t=2, precision=32, seed=0, sigma2=s2, max_iters=8)
+    budget = max(1, int(np.floor(opts.budget_frac * g.n)))
+    passes, flips = 0, 0
+    for pass_ in range(opts.max_iters + 1):
+        pm = torch.as_tensor(P).to(DEV)
+        heat, st = grass.grass_embed(ctx, dg, pm, opts, pass_=pass_)
+        h = heat.cpu().numpy().astype(np.float64)
+        ref = O.embed(g, P, k=k, t=2, seed=0, pass_=pass_, pcg_rtol=1e-10)
+        off = P == 0
+        th_ora = O.theta(s2, ref.stats["lambda_min"], ref.stats["lambda_max"], 2)
+        say(f" pass {pass_}: kappa {st['kappa']:.6g} (oracle {ref.stats['kappa']:.6g})")
+        _fp32_bar(h, ref.heat, off, _cutoff(g, P, ref, s2, 2))
+        assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
+        assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
+        passes = pass_ + 1
+        stop_gpu, stop_ora = st["kappa"] <= s2, ref.stats["kappa"] <= s2
+        if stop_gpu != stop_ora:  # only when kappa sits within the tolerance of sigma^2
+            assert abs(st["kappa"] - s2) <= 1e-4 * s2
+        if stop_gpu or pass_ == opts.max_iters:
+            break
+        _, sel = grass.grass_select(ctx, dg, pm, opts, heat, st["lambda_max"], st["lambda_min"])
+        P_gpu = pm.cpu().numpy()
+        hmax_gpu = h[off].max()
+        P_own, _, _ = O.filter_select(g, h, P, sel["theta"], hmax_gpu, sim_hops=1, budget=budget)
+        assert np.array_equal(P_gpu, P_own)  # the greedy on the GPU's scores is exact
+        P_ora, _, _ = O.filter_select(g, ref.heat, P, th_ora, ref.stats["heat_max"], sim_hops=1, budget=budget)
+        flips += _check_selection(P, P_gpu, P_ora, h / hmax_gpu, ref.heat / ref.stats["heat_max"], sel["theta"],
+                                  th_ora)
+        P = P_gpu
+    say(f"  {passes} passes, {int((P == 2).sum())} edges added, {flips} edges chosen differently by the oracle")
+    # the whole loop in one call is the same computation, bit for bit, and deterministic
     res = grass.grass_sparsify(ctx, dg, opts)
-    ref = O.sparsify(g, sigma2=opts.sigma2, k=k, t=2, seed=0)
-    mask = res.mask.cpu().numpy()
-    say("  gpu", res.summary, "\n  ora", ref.summary)
-    assert np.array_equal(mask == 1, ref.mask == 1)  # identical trees
-    diff = np.flatnonzero(mask != ref.mask)
-    assert len(diff) <= max(2, int(0.05 * (ref.mask == 2).sum())), diff
-    assert res.summary["passes"] == ref.summary["passes"]
-    # determinism: same inputs, same bits
+    assert res.summary["passes"] == passes
+    assert np.array_equal(res.mask.cpu().numpy(), P)
     res2 = grass.grass_sparsify(ctx, dg, opts)
     assert torch.equal(res.mask, res2.mask) and torch.equal(res.scores, res2.scores)
+
+
+def test_densified_pass_mesh50_k32(ctx):
+    """A densified FP32 pass at k = 32 (the benchmark's fused MFMA block-PCG kernels: product
+    with its Gram matrices, sweeps with Q'Z, updates) on a 50^3 ill-conditioned mesh against
+    the oracle, to the FP32 bar. The oracle solves to 1e-8 (1e-10 costs it 20% more CPU time;
+    either is far below the score tolerance); it runs in a thread beside the GPU work."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    g = G.mesh3d(50, 50, 50, weights=(G.W_LOGUNIFORM10, -3, 3), seed=12)
+    say("densified pass, 50^3 mesh, k = 32:", g.n, g.m)
+    tmask = O.max_spanning_tree(g)
+    r0 = O.embed(g, tmask, k=32, t=2, seed=0)
+    th = O.theta(100.0, r0.stats["lambda_min"], r0.stats["lambda_max"], 2)
+    P, acc, _ = O.filter_select(g, r0.heat, tmask, th, r0.stats["heat_max"], sim_hops=1, budget=g.n // 100)
+    assert acc == g.n // 100
+    with ThreadPoolExecutor(1) as ex:
+        fut = ex.submit(O.embed, g, P, 32, 2, 0, 1, 0, 1e-8)
+        dg = grass.to_device(g, DEV)
+        opts = grass.make_opts(k=32, t=2, precision=32, seed=0)
+        heat, st = grass.grass_embed(ctx, dg, torch.as_tensor(P).to(DEV), opts, pass_=1)
+        heat = heat.cpu().numpy().astype(np.float64)
+        ref = fut.result()
+    say(f"  pcg iters {st['pcg_iters']} (oracle {ref.stats['pcg_iters']}), resid64 {st['pcg_resid64']:.2e}, "
+        f"lambda_max {st['lambda_max']:.6g} vs {ref.stats['lambda_max']:.6g}")
+    assert st["pcg_resid64"] <= 1e-6
+    _fp32_bar(heat, ref.heat, P == 0, _cutoff(g, P, ref, 100.0, 2))
+    assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
+    assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
 
 
 def test_error_paths(ctx):
@@ -247,8 +386,8 @@ def test_error_paths(ctx):
 
 # ------------------------------------------------ full-size and larger cases
 FULL_CASES = [
-    ("c2_100cube_k32", lambda: G.config_c2(100), 32, 2),
-    ("c3_2000sq_longrange_k16_t3", lambda: G.config_c3(2000), 16, 3),
+    ("c2_100cube_k32", lambda: G.config_c2(100), 32, 2, 100.0),
+    ("c3_2000sq_longrange_k16_t3", lambda: G.config_c3(2000), 16, 3, 50.0),
 ]
 
 
@@ -256,7 +395,7 @@ FULL_CASES = [
 def test_full_size_tree_pass(ctx, case):
     """The tree pass (pass 0) of the benchmark workloads at their full sizes, in the
     launch configuration bench.py times, against the oracle's full computation."""
-    name, mk, k, t = case
+    name, mk, k, t, s2 = case
     g = mk()
     say("full-size tree pass:", name, g.n, g.m)
     dg = grass.to_device(g, DEV)
@@ -268,13 +407,8 @@ def test_full_size_tree_pass(ctx, case):
     heat = heat.cpu().numpy().astype(np.float64)
     ref = O.embed(g, tmask, k=k, t=t, seed=0, pass_=0)
     off = tmask == 0
-    err, s, r = _norm_err(heat, ref.heat, off)
-    big = off & (r >= 1e-3)
-    rel = (np.abs(s - r) / r)[big].max()
-    say(f"  max normalized err {err:.3e}, max rel err (scores >= 1e-3) {rel:.3e}, "
-        f"lambda_max {st['lambda_max']:.6g} vs {ref.stats['lambda_max']:.6g}")
-    assert err <= 1e-4
-    assert rel <= 1e-3
+    say(f"  lambda_max {st['lambda_max']:.6g} vs {ref.stats['lambda_max']:.6g}")
+    _fp32_bar(heat, ref.heat, off, _cutoff(g, tmask, ref, s2, t))
     assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
     assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
 
@@ -300,11 +434,12 @@ def test_full_size_pcg_pass_c2(ctx):
     h64, st64 = grass.grass_embed(ctx, dg, tm, grass.make_opts(k=32, t=2, precision=64, seed=0, pcg_rtol=1e-10),
                                   pass_=1)
     off = P == 0
-    err, s, r = _norm_err(heat.cpu().numpy().astype(np.float64), h64.cpu().numpy(), off)
     say(f"  pcg iters {st['pcg_iters']} (FP64 {st64['pcg_iters']}), resid64 {st['pcg_resid64']:.2e}, "
-        f"max score err {err:.3e}, lambda_max {st['lambda_max']:.6g} vs {st64['lambda_max']:.6g}")
+        f"lambda_max {st['lambda_max']:.6g} vs {st64['lambda_max']:.6g}")
     assert st["pcg_resid64"] <= 1e-6
-    assert err <= 1e-4
+    h64 = h64.cpu().numpy()
+    _fp32_bar(heat.cpu().numpy().astype(np.float64), h64, off,
+              _cutoff(g, P, None, 100.0, 2, heat=h64, stats=st64))
     assert st["lambda_max"] == pytest.approx(st64["lambda_max"], rel=1e-4)
     inP = P != 0
     degG = np.bincount(np.r_[g.src, g.dst], weights=np.r_[g.w, g.w], minlength=g.n)
@@ -326,11 +461,9 @@ def test_pcg_pass_medium_mesh(ctx):
     heat, st = grass.grass_embed(ctx, dg, torch.as_tensor(P).to(DEV), opts, pass_=1)
     ref = O.embed(g, P, k=k, t=2, seed=0, pass_=1, pcg_rtol=1e-10)
     off = P == 0
-    err, s, r = _norm_err(heat.cpu().numpy().astype(np.float64), ref.heat, off)
-    say(f"  pcg iters {st['pcg_iters']} (oracle {ref.stats['pcg_iters']}), resid64 {st['pcg_resid64']:.2e}, "
-        f"max score err {err:.3e}")
+    say(f"  pcg iters {st['pcg_iters']} (oracle {ref.stats['pcg_iters']}), resid64 {st['pcg_resid64']:.2e}")
     assert st["pcg_resid64"] <= 1e-6
-    assert err <= 1e-4
+    _fp32_bar(heat.cpu().numpy().astype(np.float64), ref.heat, off, _cutoff(g, P, ref, 100.0, 2))
     assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
 
 
