@@ -5,6 +5,7 @@ Usage: python -m paper_1911_04382_amd.build   (or call build()).
 from __future__ import annotations
 
 import os
+import shlex
 import subprocess
 import sys
 import tempfile
@@ -33,13 +34,22 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, jobs: int = 5) -> str:
-    """Compile every HIP source and link libgrass.so (always recompiles)."""
+# Host-code sanitizers (AddressSanitizer + UndefinedBehaviorSanitizer) for a CPU
+# check of the host runtime; the device code is built as usual. The runtime is
+# clang's, preloaded by the process that loads the library.
+SANITIZE_HOST = shlex.split("-Xarch_host -fsanitize=address,undefined -Xarch_host -fno-sanitize-recover=undefined "
+                            "-Xarch_host -fno-omit-frame-pointer")
+
+
+def build(verbose: bool = False, jobs: int = 5, sanitize: bool = False, out: str = LIB) -> str:
+    """Compile every HIP source and link libgrass.so (always recompiles); with
+    sanitize, the host code is instrumented and the library is written to `out`."""
     tmpdir = tempfile.mkdtemp(prefix="grass_build_")
     objs, procs = [], []
+    extra = SANITIZE_HOST if sanitize else []
     for src in SOURCES:
         obj = os.path.join(tmpdir, src.replace(".hip", ".o"))
-        cmd = [hipcc()] + HIPFLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc()] + HIPFLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -48,11 +58,11 @@ def build(verbose: bool = False, jobs: int = 5) -> str:
             _wait(procs.pop(0))
     for p in procs:
         _wait(p)
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
+    tmp = out + ".tmp"
+    cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}"] + extra + ["-o", tmp] + objs
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 def _wait(item):
