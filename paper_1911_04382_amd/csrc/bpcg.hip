@@ -7,6 +7,9 @@
 //   Z = L_T^+ R, beta = -(P'Q)^-1 (Q'Z), P = Z + P beta,
 //   P <- P chol(P'P)^-1  (keeps the block well conditioned; a direction that
 //                          becomes dependent is dropped).
+// In FP32 each inner solve starts from an orthonormal basis of the FP64 residual
+// (k_rhs_basis), and a phase that stalls turns on a stricter dependence test for the
+// rest of its solve (kStallIters).
 // X += P alpha is deferred to the pass that forms the next P (one read of P).
 // The k x k matrices are reduced in a fixed order at the end of the kernel that
 // produces them and factorised in FP64 by its last workgroup, so results are
@@ -29,6 +32,12 @@ struct BShape {
     static constexpr int RPT = G * 4;        // rows per tile
     static constexpr int CAP = RPT * 12 < 3072 ? RPT * 12 : 3072;  // staged CSR nonzeros per tile (fast path)
 };
+
+// FP32 block PCG: an inner phase longer than this has stalled, and the dependence
+// threshold of the block normalisation (relative to the own diagonal entry) that the
+// rest of that solve uses
+constexpr long long kStallIters = 256;
+constexpr double kOwnFp32 = 1e-6;
 
 // persistent blocks: block b owns a contiguous range of row tiles; ranges are
 // assigned XCD by XCD so that each XCD streams one contiguous part of the vectors
@@ -53,20 +62,27 @@ __device__ __forceinline__ void tile_range(long long ntile, int &t0, int &t1) {
 //          L^-1, so rinv = L^-T D^-1/2 (upper triangular, (P rinv)'(P rinv) = I)
 // G and P'P are symmetric positive semidefinite: they are symmetrised, the
 // elimination needs no pivoting, and a pivot below 1e-13 times the largest
-// diagonal entry marks its direction dependent. That step is skipped and the
+// diagonal entry marks its direction dependent. NORM also takes a pivot at or below
+// `own` times its own diagonal entry as dependent (own = 0 turns that off): with
+// own = 1e-6 in FP32, a direction whose part outside the span of the earlier ones
+// is under 1e-3 of its length, ten times the rounding level of an FP32 Gram. Kept,
+// such a direction is rounding noise scaled up to full length; it breaks the
+// conjugacy of the next blocks and can stall the iteration. That step is skipped and the
 // direction's row of alpha and G^-1 (its column of rinv) is zero: the solves
 // return 0 there and the direction leaves the search block. Only the leading
 // k x k block takes part; everything else is zero.
 enum SmallOp : int { SM_ALPHA = 0, SM_BETA = 1, SM_NORM = 2 };
 // ALPHA / NORM: the block holding the reduced Gram runs that small step itself
 enum TailOp : int { TAIL_STORE = 0, TAIL_SAVE = 1, TAIL_CHECK = 2, TAIL_ALPHA = 3, TAIL_NORM = 4 };
-// FP64 slots of Vecs::small, KP*KP doubles each: G^-1, reduced Gram input (two)
-enum : int { S_GINV = 0, S_IN = 2, S_SLOTS = 4 };
+// FP64 slots of Vecs::small, KP*KP doubles each: G^-1, reduced Gram input (two), and
+// for the orthonormal right-hand sides r'r, R and R^-1
+enum : int { S_GINV = 0, S_IN = 2, S_RC = 4, S_RF = 5, S_RS = 6, S_SLOTS = 7 };
 // working-precision slots of Vecs::smallT (KP*KP each)
 enum : int { T_ALPHA = 0, T_NEGALPHA = 1, T_BETA = 2, T_RINV = 3 };
 
 template <typename T, int KP, int OP, int NT>
-__device__ void small_op(int k, const double *in, double *__restrict__ ginv, T *__restrict__ outT) {
+__device__ void small_op(int k, const double *in, double *__restrict__ ginv, T *__restrict__ outT,
+                         double own = 0.0) {
     constexpr int KK = KP * KP;
     const int tid = threadIdx.x;
     if constexpr (OP == SM_BETA) {
@@ -171,7 +187,8 @@ __device__ void small_op(int k, const double *in, double *__restrict__ ginv, T *
         for (int b = 0; b < CPT; b++) pr[b] = s_prow[buf][tc + CG * b < W ? tc + CG * b : 0];
 #pragma unroll
         for (int a = 0; a < RPT; a++) pc[a] = s_pcol[buf][tr + RG * a < KP ? tr + RG * a : 0];
-        const bool ok = d > tol;  // uniform: every thread reads the same pivot
+        // uniform: every thread reads the same pivot and diagonal entry
+        const bool ok = d > tol && (OP != SM_NORM || d > own * in[jj * KP + jj]);
         if (ok) {
             const double rp = 1.0 / d;
 #pragma unroll
@@ -220,8 +237,8 @@ __device__ void small_op(int k, const double *in, double *__restrict__ ginv, T *
 }
 
 template <typename T, int KP, int OP>
-__global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ sm, T *__restrict__ outT) {
-    small_op<T, KP, OP, kThreads>(k, sm + S_IN * KP * KP, sm + S_GINV * KP * KP, outT);
+__global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ sm, T *__restrict__ outT, double own) {
+    small_op<T, KP, OP, kThreads>(k, sm + S_IN * KP * KP, sm + S_GINV * KP * KP, outT, own);
 }
 
 template <typename T>
@@ -235,6 +252,7 @@ struct Tail {
     int op;
     T *outT;            // ALPHA / NORM: the small-matrix outputs
     double *ginv;       // ALPHA: G^-1 for the later BETA step
+    double own;         // NORM: dependence threshold relative to the own diagonal entry
 };
 
 // SAVE / STORE of the reduced total (tot in LDS, width doubles)
@@ -676,7 +694,7 @@ __global__ __launch_bounds__(NT) void k_mf_pupdate(long long n, int k, const flo
     gram.flush(s_w, tl.part + (long long)blockIdx.x * KK);
     if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) {
         if (tl.op == TAIL_NORM)
-            small_op<float, KP, SM_NORM, NT>(k, s_w, tl.ginv, tl.outT);
+            small_op<float, KP, SM_NORM, NT>(k, s_w, tl.ginv, tl.outT, tl.own);
         else
             tail_finish<KP>(s_w, KK, k, tl.op, tl.vec);
     }
@@ -712,6 +730,100 @@ template <typename T>
 __global__ void k_copy_vec(long long nk, const T *__restrict__ a, T *__restrict__ b) {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nk; i += (long long)gridDim.x * blockDim.x)
         b[i] = a[i];
+}
+
+// ------------------------------------------- orthonormal right-hand sides (FP32)
+// The residual block of a later power step is dominated by the few largest
+// generalized eigenvectors, so its k columns can agree to within FP32 rounding:
+// the working-precision Gram of such a block cannot be factorised and the block
+// PCG stalls. Each inner solve therefore starts from an orthonormal basis of the
+// FP64 residual, r = Q R (Cholesky QR in FP64), solves L_P Y = Q in working
+// precision and hands z = Y R back to the FP64 outer step. Block CG spans the same
+// space for r and Q; only the rounding differs.
+//
+// Cholesky of C = r'r (k x k, ld k, symmetrised): R upper triangular (ld KP) with
+// R'R = C on the kept directions, S = R^-1 on them (ld KP) and qn[j] = 1. A pivot
+// at or below 1e-12 times its own diagonal entry (the column's part outside the
+// span of the earlier ones is below 1e-6 of its length), or a zero column, drops
+// direction j: row j of R, column j of S and qn[j] are 0, and column j of r is
+// carried by the kept directions alone.
+template <int KP>
+__global__ __launch_bounds__(kThreads) void k_rhs_basis(int k, const double *__restrict__ C, double *__restrict__ R,
+                                                        double *__restrict__ S, double *__restrict__ qn) {
+    // a: the elimination in place; R ends in the upper triangle, S (upper triangular)
+    // is kept transposed in the strict lower triangle and its diagonal in sd
+    __shared__ double a[KP][KP + 1];
+    __shared__ double sd[KP];
+    __shared__ int live[KP];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < KP * KP; e += kThreads) {
+        const int i = e / KP, l = e % KP;
+        a[i][l] = (i < k && l < k) ? 0.5 * (C[i * k + l] + C[l * k + i]) : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < k; j++) {
+        const double dj = a[j][j];
+        const bool ok = dj > 0.0 && dj > 1e-12 * C[j * k + j];  // uniform
+        __syncthreads();  // every thread has read the pivot before row j is scaled
+        if (ok) {
+            const double rs = 1.0 / sqrt(dj);
+            for (int l = j + tid; l < k; l += kThreads) a[j][l] *= rs;
+        }
+        if (tid == 0) live[j] = ok ? 1 : 0;
+        __syncthreads();
+        if (ok) {
+            for (int e = tid; e < KP * KP; e += kThreads) {
+                const int i = e / KP, l = e % KP;
+                if (i > j && l > j && i < k && l < k) a[i][l] -= a[j][i] * a[j][l];
+            }
+        }
+        __syncthreads();
+    }
+    // S: back substitution on the kept rows, one column per thread (column j of S is
+    // row j of the lower triangle, written only by thread j)
+    if (tid < k && live[tid]) {
+        const int j = tid;
+        for (int i = 0; i < j; i++) a[j][i] = 0.0;
+        sd[j] = 1.0 / a[j][j];
+        for (int i = j - 1; i >= 0; i--) {
+            if (!live[i]) continue;
+            double acc = a[i][j] * sd[j];
+            for (int l = i + 1; l < j; l++) acc += a[i][l] * a[j][l];
+            a[j][i] = -acc / a[i][i];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < KP * KP; e += kThreads) {
+        const int i = e / KP, l = e % KP;
+        const bool in = i < k && l < k && live[i] && live[l];
+        R[e] = (i < k && l < k && live[i] && l >= i) ? a[i][l] : 0.0;
+        S[e] = in && l > i ? a[l][i] : (in && l == i ? sd[i] : 0.0);
+    }
+    if (tid < kMaxK) qn[tid] = (tid < k && live[tid]) ? 1.0 : 0.0;
+}
+
+// out = in M for an upper-triangular k x k M (FP64, ld KP), row by row in FP64
+template <typename TI, typename TO, int KP>
+__global__ __launch_bounds__(kThreads) void k_basis_map(long long n, int k, const TI *__restrict__ in,
+                                                        const double *__restrict__ M, TO *__restrict__ out, int nblk) {
+    constexpr int G = kThreads / KP;
+    constexpr int RPB = G * kRowsPerGroup;
+    __shared__ double sm[KP * KP];
+    const int bid = xcd_block(blockIdx.x, gridDim.x);
+    if (bid >= nblk) return;  // whole block
+    for (int e = threadIdx.x; e < KP * KP; e += kThreads) sm[e] = M[e];
+    __syncthreads();
+    const int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    if (j >= k) return;
+    const long long r0 = (long long)bid * RPB;
+    for (int i = g; i < RPB; i += G) {
+        const long long v = r0 + i;
+        if (v >= n) break;
+        const TI *row = in + v * k;
+        double acc = 0.0;
+        for (int l = 0; l <= j; l++) acc += (double)row[l] * sm[l * KP + j];
+        out[v * k + j] = (TO)acc;
+    }
 }
 
 }  // namespace
@@ -794,9 +906,9 @@ static Tail<T> save_tail(Vecs<T> &v, const Dims &d) {
     return tl;
 }
 template <typename T, int KP, int OP>
-static void launch_small(const Dims &d, Vecs<T> &v, hipStream_t s) {
+static void launch_small(const Dims &d, Vecs<T> &v, hipStream_t s, double own = 0.0) {
     ProfScope ps(PK_SMALL, 0.0, s);
-    hipLaunchKernelGGL((k_small<T, KP, OP>), dim3(1), dim3(kThreads), 0, s, d.k, v.small, v.smallT);
+    hipLaunchKernelGGL((k_small<T, KP, OP>), dim3(1), dim3(kThreads), 0, s, d.k, v.small, v.smallT, own);
 }
 
 // R -= Q alpha and the convergence count
@@ -815,13 +927,14 @@ static void launch_rupdate(const Dims &d, Vecs<T> &v, Tail<T> tl, hipStream_t s)
 // X += P alpha, P = Z + P beta and the Gram of the new P (with MFMA also rinv from
 // it, in the block that completes the Gram)
 template <typename T, int KP>
-static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s) {
+static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s, double own) {
     const int KK = KP * KP;
     ProfScope ps(PK_PUPDATE, 5.0 * d.n * d.k * sizeof(T), s);
     Tail<T> tl = save_tail(v, d);
     if constexpr (UseMF<T, KP>::value) {
         tl.op = TAIL_NORM;
         tl.outT = v.smallT;
+        tl.own = own;
     }
     if constexpr (UseMF<T, KP>::value)
         hipLaunchKernelGGL((k_mf_pupdate<KP, 512>), dim3(kMfGramBlocks), dim3(512), 0, s, d.n, d.k,
@@ -842,6 +955,36 @@ static void launch_rowmul(const Dims &d, const T *M, const T *In, const T *C, T 
                            Out);
 }
 
+// v.r = Q = r64 S with r64 = Q R (Cholesky QR in FP64, R and S in v.small); the
+// squared norms of Q's columns in red[RED_QN]
+template <typename T>
+static void rhs_basis(const Dims &d, Vecs<T> &v, hipStream_t s) {
+    const long long KK = (long long)d.kp * d.kp;
+    double *C = v.small + S_RC * KK, *R = v.small + S_RF * KK, *S = v.small + S_RS * KK;
+    const int nbv = vec_blocks(d);
+    ProfScope ps(PK_RESID64, (double)d.n * d.k * (16 + sizeof(T)), s);
+    block_gram<double>(d, v.r64, v.r64, v.gpart, v.tcnt, C, s);
+    KP_DISPATCH(d.kp, {
+        hipLaunchKernelGGL(k_rhs_basis<KP>, dim3(1), dim3(kThreads), 0, s, d.k, C, R, S, v.red + RED_QN * kMaxK);
+        hipLaunchKernelGGL((k_basis_map<double, T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, v.r64,
+                           S, v.r, nbv);
+    });
+    GR_CHECK_LAUNCH();
+}
+
+// z64 = Y R for the inner solution Y = v.dx on the basis of rhs_basis
+template <typename T>
+static void basis_back(const Dims &d, Vecs<T> &v, hipStream_t s) {
+    const long long KK = (long long)d.kp * d.kp;
+    const int nbv = vec_blocks(d);
+    ProfScope ps(PK_RESID64, (double)d.n * d.k * (8 + sizeof(T)), s);
+    KP_DISPATCH(d.kp, {
+        hipLaunchKernelGGL((k_basis_map<T, double, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, v.dx,
+                           v.small + S_RF * KK, v.z64, nbv);
+    });
+    GR_CHECK_LAUNCH();
+}
+
 template <typename T>
 SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s,
                     const double *b64) {
@@ -855,8 +998,18 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     // r = b - L_P x with x = 0; its norms are the reference of the first inner phase
     info.resid64 = true_residual<T>(t, v, d, b, s, b64);
     if (info.resid64 <= pp.rtol) return info;
+    // FP32 working precision: every inner solve runs on an orthonormal basis of the
+    // FP64 residual (FP64 keeps the columns apart by itself)
+    const bool basis = v.z64 != nullptr;
+    // FP32: an inner phase that runs kStallIters iterations without every column
+    // converging ends there (the FP64 step takes the partial solution), and the rest of
+    // the solve normalises its blocks with the dependence threshold kOwnFp32
+    constexpr bool fp32 = std::is_same<T, float>::value;
+    double own = 0.0;
+    long long phase0 = 0;  // iterations before the current inner phase
     // a fresh search block: P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
     auto start_block = [&]() {
+        if (basis) rhs_basis<T>(d, v, s);
         tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
         hipLaunchKernelGGL(k_copy_vec<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.z, v.p);
         KP_DISPATCH(d.kp, {
@@ -864,7 +1017,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
                 ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
                 launch_gram<T, KP, 1>(d, v.p, v.p, nullptr, tsave, s);
             }
-            launch_small<T, KP, SM_NORM>(d, v, s);
+            launch_small<T, KP, SM_NORM>(d, v, s, own);
             launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
         });
         GR_CHECK_LAUNCH();
@@ -875,7 +1028,8 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     tcheck.cnt = v.tcnt;
     tcheck.op = TAIL_CHECK;
     tcheck.vec = v.red + RED_RR * kMaxK;
-    tcheck.rr0 = v.red + RED_RN * kMaxK;  // squared norms at the last replacement
+    // squared norms of the inner solve's right-hand sides
+    tcheck.rr0 = v.red + (basis ? RED_QN : RED_RN) * kMaxK;
     tcheck.count = cnt;
     tcheck.tol2 = pp.itol * pp.itol;
     long long it = 0;
@@ -900,13 +1054,17 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
             GR_CHECK_LAUNCH();
             const bool last = it >= pp.max_it;
             if (last || (it & 3) == 0) {
-                if (last || read_i32(cnt, s) == 0) {
+                const bool done = last || read_i32(cnt, s) == 0;
+                const bool stall = fp32 && !done && own == 0.0 && it - phase0 >= kStallIters;
+                if (done || stall) {
                     // every vector's recursive residual fell by itol since the inner
-                    // solve started: X += P alpha completes z ~ L_P^-1 r, which the FP64
-                    // flexible-CG step turns into its next direction; the inner solve
-                    // then restarts from the new FP64 residual
+                    // solve started (or the phase stalled): X += P alpha completes
+                    // z ~ L_P^-1 r, which the FP64 flexible-CG step turns into its next
+                    // direction; the inner solve then restarts from the new FP64 residual
+                    if (stall) own = kOwnFp32;
                     launch_rowmul<T, KP, true>(d, v.smallT + T_ALPHA * KK, v.p, v.dx, v.dx, s);
-                    info.resid64 = fcg_outer_step<T>(t, v, d, fresh, s);
+                    if (basis) basis_back<T>(d, v, s);
+                    info.resid64 = fcg_outer_step<T>(t, v, d, fresh, s, basis ? v.z64 : nullptr);
                     fresh = false;
                     checked = false;
                     if (info.resid64 <= pp.rtol) {
@@ -933,8 +1091,8 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
                     }
                     launch_small<T, KP, SM_BETA>(d, v, s);
                 }
-                launch_pupdate<T, KP>(d, v, s);
-                if constexpr (!UseMF<T, KP>::value) launch_small<T, KP, SM_NORM>(d, v, s);
+                launch_pupdate<T, KP>(d, v, s, own);
+                if constexpr (!UseMF<T, KP>::value) launch_small<T, KP, SM_NORM>(d, v, s, own);
                 launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
             }
             GR_CHECK_LAUNCH();
@@ -942,6 +1100,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
         if (stop) break;
         if (restart) {
             info.outer++;
+            phase0 = it;
             start_block();
         }
     }

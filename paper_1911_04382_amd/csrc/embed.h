@@ -9,8 +9,9 @@ namespace grass {
 enum : int {
     RED_NUM = 0, RED_DEN, RED_LMAX, RED_RR, RED_BN, RED_RN, RED_MEAN,
     // the FP64 flexible-CG outer iteration of the L_P solve (per column): z'A d_prev,
-    // d'r, d'A d, the previous d'A d, its alpha and beta
-    RED_ZAD, RED_DR, RED_DAD, RED_DADP, RED_FA, RED_FB,
+    // d'r, d'A d, the previous d'A d, its alpha and beta; squared norms of the inner
+    // solve's orthonormal right-hand sides (1, or 0 for a dropped direction)
+    RED_ZAD, RED_DR, RED_DAD, RED_DADP, RED_FA, RED_FB, RED_QN,
     RED_SLOTS = 16
 };
 // u64 slots in Vecs::u64s
@@ -72,11 +73,11 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
 // red[RED_RN]; returns max_j ||r_j|| / ||b_j|| (b norms in red[RED_BN]).
 template <typename T>
 double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, hipStream_t s, const double *b64 = nullptr);
-// One FP64 flexible-CG step of the L_P solve with z = v.dx from the inner block PCG
-// (first: start the recurrence): x64, r64, v.r and the norms in red[RED_RN] are
-// updated, v.dx is cleared; returns max_j ||r_j|| / ||b_j||.
+// One FP64 flexible-CG step of the L_P solve with z = v.dx from the inner block PCG,
+// or z = z64 when given (first: start the recurrence): x64, r64, v.r and the norms in
+// red[RED_RN] are updated, v.dx is cleared; returns max_j ||r_j|| / ||b_j||.
 template <typename T>
-double fcg_outer_step(Topo &t, Vecs<T> &v, const Dims &d, bool first, hipStream_t s);
+double fcg_outer_step(Topo &t, Vecs<T> &v, const Dims &d, bool first, hipStream_t s, const double *z64 = nullptr);
 
 // Score every edge: heat (optional output), FP64 per-vector sums over E and over P,
 // max heat over the edges not in P. Then reduce to lambda_max (host reads).

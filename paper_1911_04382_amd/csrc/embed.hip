@@ -1322,11 +1322,12 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
     v.ad64 = a.take<double>(nk);
     v.w64 = a.take<double>(nk);
     v.b64 = a.take<double>(nk);
+    v.z64 = std::is_same<T, double>::value ? nullptr : a.take<double>(nk);
     long long parts = std::max<long long>({(long long)lap_blocks(d) + 8, (long long)vec_blocks(d) + 8, d.ntiles, 2ll * std::max(score_blocks(d), score_blocks(d, true)),
                                            (long long)gauss_blocks(d)});
     v.part = a.take<double>(parts * d.kp + 64);
     v.part2 = a.take<double>(64 * d.kp + 64);
-    v.small = a.take<double>(4 * d.kp * d.kp + 64);  // Cholesky factor, pivots, Gram input
+    v.small = a.take<double>(7 * d.kp * d.kp + 64);  // G^-1, Gram input, right-hand-side basis
     v.smallT = a.take<T>(4 * d.kp * d.kp + 64);      // alpha, -alpha, beta, R^-1
     v.gpart = a.take<double>(bpcg_part_doubles(d));
     v.tcnt = a.take<int>(bpcg_counters(d));
@@ -1523,23 +1524,31 @@ double true_residual(Topo &t, Vecs<T> &v, const Dims &d, const T *b, hipStream_t
 }
 
 template <typename T>
-double fcg_outer_step(Topo &t, Vecs<T> &v, const Dims &d, bool first, hipStream_t s) {
+double fcg_outer_step(Topo &t, Vecs<T> &v, const Dims &d, bool first, hipStream_t s, const double *z64) {
     const int nbv = vec_blocks(d);
     double *red = v.red;
     {
         ProfScope ps(PK_RESID64, 4.0 * (d.n + 1) + 12.0 * d.p_nnz + (double)d.n * d.k * (sizeof(T) + 56), s);
         KP_DISPATCH(d.kp, {
             // w = A z (with z'Ad_prev after the first step)
-            hipLaunchKernelGGL((k_apply64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow,
-                               t.pcol, t.pval64, v.dx, v.w64, first ? (const double *)nullptr : v.ad64, 0, v.part,
-                               nbv);
+            const double *adp = first ? (const double *)nullptr : v.ad64;
+            if (z64)
+                hipLaunchKernelGGL((k_apply64<double, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k,
+                                   t.prow, t.pcol, t.pval64, z64, v.w64, adp, 0, v.part, nbv);
+            else
+                hipLaunchKernelGGL((k_apply64<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.prow,
+                                   t.pcol, t.pval64, v.dx, v.w64, adp, 0, v.part, nbv);
             GR_CHECK_LAUNCH();
             if (!first) col_sum<T>(d, v, v.part, nbv, KP, 0, red + RED_ZAD * kMaxK, s);
             hipLaunchKernelGGL(k_fcg64_coef, dim3(1), dim3(kMaxK), 0, s, d.k, first ? (int)FC64_FIRST : (int)FC64_NEXT,
                                red);
             // d = z - beta d, Ad = w - beta Ad; d'r, d'Ad; alpha
-            hipLaunchKernelGGL((k_fcg64_dir<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, (int)first,
-                               red + RED_FB * kMaxK, v.dx, v.w64, v.r64, v.d64, v.ad64, v.part, nbv);
+            if (z64)
+                hipLaunchKernelGGL((k_fcg64_dir<double, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k,
+                                   (int)first, red + RED_FB * kMaxK, z64, v.w64, v.r64, v.d64, v.ad64, v.part, nbv);
+            else
+                hipLaunchKernelGGL((k_fcg64_dir<T, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k,
+                                   (int)first, red + RED_FB * kMaxK, v.dx, v.w64, v.r64, v.d64, v.ad64, v.part, nbv);
             GR_CHECK_LAUNCH();
             col_sum<T>(d, v, v.part, nbv, 2 * KP, 0, red + RED_DR * kMaxK, s);
             col_sum<T>(d, v, v.part, nbv, 2 * KP, KP, red + RED_DAD * kMaxK, s);
@@ -1663,7 +1672,7 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
                                 unsigned long long *, hipStream_t, const T *, double *, int *, double *,         \
                                 const double *, T *);                                                            \
     template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, hipStream_t, const double *);  \
-    template double fcg_outer_step<T>(Topo &, Vecs<T> &, const Dims &, bool, hipStream_t);                      \
+    template double fcg_outer_step<T>(Topo &, Vecs<T> &, const Dims &, bool, hipStream_t, const double *);        \
     template SolveInfo pcg_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const grass_opts &,         \
                                     hipStream_t, const double *);                                                \
     template void score_edges<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, hipStream_t, const double *);  \

@@ -16,7 +16,7 @@ enum ProfKind : int {
     PK_PUPDATE,     // block PCG: X += P alpha, P = Z + P beta and P'P
     PK_ROWMUL,      // block PCG: P = P R^-1 (and the last X += P alpha)
     PK_SMALL,       // block PCG: k x k FP64 steps (alpha, beta, R^-1), one wave
-    PK_RESID64,     // FP64 refinement residual (k_resid64)
+    PK_RESID64,     // FP64 outer iteration: residual, flexible-CG step, right-hand-side basis
     PK_START,       // start vectors
     PK_SELECT,      // candidate filter, sort and greedy
     PK_COUNT

@@ -126,6 +126,7 @@ struct Vecs {
     // the FP64 outer iteration of the L_P solve: solution, residual, direction, A d, A z
     double *x64 = nullptr, *r64 = nullptr, *d64 = nullptr, *ad64 = nullptr, *w64 = nullptr;  // [n*k]
     double *b64 = nullptr;  // [n*k] FP64 right-hand side L_G x64 of a power step after an L_P solve
+    double *z64 = nullptr;  // [n*k] inner-solve result mapped back from the orthonormal basis (FP32 only)
     // reductions
     double *part = nullptr;   // [ntiles*kp*2] per-block partials
     double *part2 = nullptr;  // [64*kp] first-stage column sums

@@ -467,6 +467,39 @@ def test_pcg_pass_medium_mesh(ctx):
     assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
 
 
+@pytest.mark.parametrize("k", [16, 32])
+def test_fp32_pass_with_nearly_parallel_right_hand_sides(ctx, k):
+    """The second power step of a pass solves L_P x = L_G h1 with h1 = L_P^+ L_G h0
+    (eq. 29): its k right-hand sides are dominated by the few largest generalized
+    eigenvectors and agree to within FP32 rounding. On this 42^3 mesh (U[1,10), one of
+    the 3-D graphs of the mixed-size batch) the FP32 solves of the first densified pass
+    reach pcg_rtol only when the inner block PCG works on an orthonormal basis of the
+    FP64 residual and drops the directions its FP32 Gram cannot tell apart. The pass's
+    heats are checked against the FP64 path on the same P, and a whole sparsify call
+    must end with every solve at pcg_rtol."""
+    g = G.mesh3d(42, 42, 42, (G.W_UNIFORM, 1.0, 10.0), seed=7)
+    say(f"FP32 pass, 42^3 mesh U[1,10), k = {k}", g.n, g.m)
+    dg = grass.to_device(g, DEV)
+    tm = grass.grass_spanning_tree(ctx, dg)
+    o32 = grass.make_opts(k=k, t=2, sigma2=100.0, precision=32, seed=0)
+    heat0, st0 = grass.grass_embed(ctx, dg, tm, o32, pass_=0)
+    grass.grass_select(ctx, dg, tm, o32, heat0, st0["lambda_max"], st0["lambda_min"])
+    P = tm.cpu().numpy()
+    assert (P == 2).sum() > 100
+    heat, st = grass.grass_embed(ctx, dg, tm, o32, pass_=1)
+    h64, st64 = grass.grass_embed(ctx, dg, tm, grass.make_opts(k=k, t=2, sigma2=100.0, precision=64, seed=0,
+                                                                 pcg_rtol=1e-10), pass_=1)
+    say(f"  pcg iters {st['pcg_iters']} (FP64 {st64['pcg_iters']}), resid64 {st['pcg_resid64']:.2e}")
+    assert st["pcg_resid64"] <= 1e-6
+    h64 = h64.cpu().numpy()
+    _fp32_bar(heat.cpu().numpy().astype(np.float64), h64, P == 0,
+              _cutoff(g, P, None, 100.0, 2, heat=h64, stats=st64))
+    assert st["lambda_max"] == pytest.approx(st64["lambda_max"], rel=1e-4)
+    r = grass.grass_sparsify(ctx, dg, o32)
+    say(f"  sparsify: {r.summary['passes']} passes, {r.summary['pcg_iters']} pcg iters")
+    assert all(tr["pcg_resid64"] <= 1e-6 for tr in r.trace[1:])
+
+
 @pytest.mark.parametrize("k,prec", [(32, 32), (16, 32), (24, 32), (8, 32), (64, 32), (5, 64), (32, 64)])
 def test_block_gram_kernel_layout(ctx, k, prec):
     """The Gram kernel of the block PCG (MFMA accumulators for FP32, k in 9..32)
