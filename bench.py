@@ -229,13 +229,27 @@ def run_batch(args, grass, torch):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     ws = grass.batch_workspace(dgs, opts, args.workers)
-    t0 = time.perf_counter()
-    log(f"batch path: {len(dgs)} graphs, {args.workers} workers ...")
-    rc, out = grass.grass_sparsify_batch(ctx, dgs, opts, workers=args.workers, ws=ws)
-    torch.cuda.synchronize()
-    t_batch = time.perf_counter() - t0
-    log(f"batch path: done in {t_batch:.1f} s")
-    same = all(torch.equal(a.mask, b.mask) and torch.equal(a.scores, b.scores) for a, b in zip(out, plain))
+
+    def batch(mode, label):
+        ctx.set_launch_mode(mode, 0)
+        ctx.launch_stats(reset=True)
+        t0 = time.perf_counter()
+        log(f"batch path ({label}): {len(dgs)} graphs, {args.workers} workers ...")
+        rc, out = grass.grass_sparsify_batch(ctx, dgs, opts, workers=args.workers, ws=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.launch_stats()
+        log(f"batch path ({label}): done in {dt:.1f} s, {st}")
+        same = all(torch.equal(a.mask, b.mask) and torch.equal(a.scores, b.scores) for a, b in zip(out, plain))
+        return dt, out, same, st
+
+    # worker pool, kernel by kernel (host reads the loop state every 4th iteration)
+    t_kern, _, same_kern, st_kern = batch(grass.LAUNCH_KERNELS, "kernel by kernel")
+    # worker pool with captured chunks and device-side loop control; the first run
+    # also tunes chunks per read for each size class, the second reuses the choices
+    t_cold, _, same_cold, st_cold = batch(grass.LAUNCH_CAPTURED, "captured, tuning")
+    t_batch, out, same, st = batch(grass.LAUNCH_CAPTURED, "captured, tuned")
+    same = same and same_kern and same_cold
     scored = sum(r.summary["scored_edges"] for r in out)
     line = {"metric": "off-tree edges scored/sec, batch of independent graphs", "value": scored / t_batch,
             "unit": "edges/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -243,7 +257,9 @@ def run_batch(args, grass, torch):
                                    "[1e3, 2e5], U[1,10), k=16, t=2, sigma^2=100",
                        "graphs": len(gs), "nodes": sum(g.n for g in gs), "workers": args.workers,
                        "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
-            "batch_s": t_batch, "plain_s": t_plain, "plain_value": scored / t_plain, "speedup": t_plain / t_batch,
+            "batch_s": t_batch, "batch_tuning_s": t_cold, "batch_kernels_s": t_kern, "plain_s": t_plain,
+            "plain_value": scored / t_plain, "speedup": t_plain / t_batch, "speedup_vs_kernels": t_kern / t_batch,
+            "launch_stats": {"captured": st, "captured_tuning": st_cold, "kernels": st_kern},
             "identical_to_plain": same,
             "statuses": {str(k): sum(1 for r in out if r.status == k) for k in sorted({r.status for r in out})}}
     ctx.close()

@@ -185,6 +185,35 @@ grass_status grass_sparsify_batch(grass_ctx *ctx, int32_t count, const grass_gra
                                   int32_t opts_count, int32_t workers, void *workspace, size_t ws_bytes,
                                   grass_result *results, grass_status *statuses, void *stream);
 
+/* Launch schedule of the L_P solves' inner block-PCG loop on the concurrent paths
+ * (grass_sparsify_batch, and servers created afterwards); the single-graph entry
+ * points always launch kernel by kernel. The loop's decisions (iteration count and
+ * cap, the end of an inner phase, the stall rule of FP32 solves) are taken on the
+ * device in every mode.
+ *   GRASS_LAUNCH_KERNELS: kernel by kernel, the host reading the loop state every
+ *     4th iteration (8 bytes).
+ *   GRASS_LAUNCH_CAPTURED (default): with FP32 and k of 16 or 32, four iterations
+ *     are captured once per solve as a hipGraph and replayed chunks_per_read times
+ *     between host reads; kernels replayed after a phase has ended return at once,
+ *     so every output is the same as kernel by kernel. chunks_per_read 0 (default)
+ *     lets the context's autotuner choose per size class (node count in powers of
+ *     two, k): it times inner phases with 1, 2, 4 or 8 chunks and with kernel-by-
+ *     kernel launches, three phases each, and keeps the fastest.
+ * Other k and FP64 run kernel by kernel. Returns GRASS_ERR_INVALID for an unknown
+ * mode or chunks_per_read outside 0..64. */
+enum { GRASS_LAUNCH_KERNELS = 0, GRASS_LAUNCH_CAPTURED = 1 };
+grass_status grass_set_launch_mode(grass_ctx *ctx, int32_t mode, int32_t chunks_per_read);
+/* Counters of the block-PCG loops run through the launch schedule above since the
+ * context was created or last reset (reset != 0 clears them after the copy):
+ * iterations, host reads of the loop state, graph replays and captures. */
+typedef struct {
+    int64_t iterations;
+    int64_t host_reads;
+    int64_t graph_replays;
+    int64_t captures;
+} grass_launch_stats;
+grass_status grass_launch_stats_read(grass_ctx *ctx, grass_launch_stats *out, int32_t reset);
+
 /* Serving: a queue of sparsify requests on one device with continuous batching.
  * grass_server_create preallocates a device arena of arena_bytes (the admission
  * budget) and starts `workers` host workers, each with its own HIP stream.

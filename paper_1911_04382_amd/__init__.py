@@ -20,6 +20,7 @@ OK, NOT_CONVERGED = 0, 1
 ERR_INVALID, ERR_DISCONNECTED, ERR_OOM, ERR_DEVICE, ERR_UNIMPLEMENTED, ERR_CANCELLED = -1, -2, -3, -4, -5, -6
 ERR_SOLVE, ERR_NONFINITE = -7, -8
 PASS_SOLVE_FAILED = 1
+LAUNCH_KERNELS, LAUNCH_CAPTURED = 0, 1
 STATUS_NAMES = {0: "OK", 1: "NOT_CONVERGED", -1: "ERR_INVALID", -2: "ERR_DISCONNECTED", -3: "ERR_OOM",
                 -4: "ERR_DEVICE", -5: "ERR_UNIMPLEMENTED", -6: "ERR_CANCELLED", -7: "ERR_SOLVE",
                 -8: "ERR_NONFINITE"}
@@ -100,6 +101,11 @@ class grass_kernel_stats(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double)]
 
 
+class grass_launch_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("host_reads", ctypes.c_int64), ("graph_replays", ctypes.c_int64),
+                ("captures", ctypes.c_int64)]
+
+
 class grass_req_info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_end", ctypes.c_double), ("footprint", ctypes.c_size_t)]
@@ -177,6 +183,10 @@ def load_library(path: str = LIB_PATH):
     L.grass_profile_enable.restype = st
     L.grass_profile_read.argtypes = [vp, ctypes.POINTER(grass_kernel_stats), i32]
     L.grass_profile_read.restype = i32
+    L.grass_set_launch_mode.argtypes = [vp, i32, i32]
+    L.grass_set_launch_mode.restype = st
+    L.grass_launch_stats_read.argtypes = [vp, ctypes.POINTER(grass_launch_stats), i32]
+    L.grass_launch_stats_read.restype = st
     L.grass_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(grass_graph), ctypes.POINTER(grass_opts), i32, i32]
     L.grass_batch_workspace_bytes.restype = ctypes.c_size_t
     L.grass_sparsify_batch.argtypes = [vp, i32, ctypes.POINTER(grass_graph), ctypes.POINTER(grass_opts), i32, i32,
@@ -255,6 +265,18 @@ class Context:
         got = self.lib.grass_profile_read(self.h, arr, n)
         return {arr[i].name.decode(): {"launches": arr[i].launches, "ms": arr[i].total_ms,
                                        "alg_bytes": arr[i].alg_bytes} for i in range(got)}
+
+    def set_launch_mode(self, mode: int, chunks_per_read: int = 0):
+        """grass_set_launch_mode: LAUNCH_KERNELS or LAUNCH_CAPTURED (chunks of four
+        block-PCG iterations replayed chunks_per_read times between host reads; 0 lets
+        the context's autotuner choose) for the batch and server paths."""
+        self.check(self.lib.grass_set_launch_mode(self.h, int(mode), int(chunks_per_read)))
+
+    def launch_stats(self, reset: bool = False) -> dict:
+        """grass_launch_stats_read: iterations, host reads, graph replays, captures."""
+        out = grass_launch_stats()
+        self.check(self.lib.grass_launch_stats_read(self.h, ctypes.byref(out), 1 if reset else 0))
+        return {f[0]: getattr(out, f[0]) for f in out._fields_}
 
     def check(self, rc):
         if rc < 0:

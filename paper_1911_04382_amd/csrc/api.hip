@@ -16,6 +16,7 @@
 
 namespace grass {
 thread_local Profiler *g_prof = nullptr;
+thread_local LaunchSched *g_sched = nullptr;
 namespace {
 
 // Everything one call needs, planned over one arena.
@@ -797,6 +798,33 @@ grass_status grass_gram(grass_ctx *ctx, int64_t n, int32_t k, int32_t precision,
         GR_HIP(hipStreamSynchronize(s));
         return GRASS_OK;
     });
+}
+
+grass_status grass_set_launch_mode(grass_ctx *ctx, int32_t mode, int32_t chunks_per_read) {
+    if (!ctx) return GRASS_ERR_INVALID;
+    if ((mode != GRASS_LAUNCH_KERNELS && mode != GRASS_LAUNCH_CAPTURED) || chunks_per_read < 0 ||
+        chunks_per_read > 64) {
+        ctx->last_error = "launch mode must be GRASS_LAUNCH_KERNELS or GRASS_LAUNCH_CAPTURED, chunks_per_read in 0..64";
+        return GRASS_ERR_INVALID;
+    }
+    ctx->launch_mode = mode;
+    ctx->launch_chunks = chunks_per_read;
+    return GRASS_OK;
+}
+
+grass_status grass_launch_stats_read(grass_ctx *ctx, grass_launch_stats *out, int32_t reset) {
+    if (!ctx || !out) return GRASS_ERR_INVALID;
+    out->iterations = ctx->lstats.iterations.load();
+    out->host_reads = ctx->lstats.host_reads.load();
+    out->graph_replays = ctx->lstats.replays.load();
+    out->captures = ctx->lstats.captures.load();
+    if (reset) {
+        ctx->lstats.iterations = 0;
+        ctx->lstats.host_reads = 0;
+        ctx->lstats.replays = 0;
+        ctx->lstats.captures = 0;
+    }
+    return GRASS_OK;
 }
 
 grass_status grass_profile_enable(grass_ctx *ctx, uint32_t kinds) {

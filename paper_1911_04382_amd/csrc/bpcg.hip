@@ -21,6 +21,11 @@
 #include "gram.h"
 #include "lap.h"
 #include "profiler.h"
+#include "sched.h"
+
+#include <chrono>
+#include <climits>
+#include <cstddef>
 
 namespace grass {
 
@@ -237,8 +242,9 @@ __device__ void small_op(int k, const double *in, double *__restrict__ ginv, T *
 }
 
 template <typename T, int KP, int OP>
-__global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ sm, T *__restrict__ outT, double own) {
-    small_op<T, KP, OP, kThreads>(k, sm + S_IN * KP * KP, sm + S_GINV * KP * KP, outT, own);
+__global__ __launch_bounds__(kThreads) void k_small(int k, double *__restrict__ sm, T *__restrict__ outT,
+                                                    const LoopCtl *__restrict__ loop) {
+    small_op<T, KP, OP, kThreads>(k, sm + S_IN * KP * KP, sm + S_GINV * KP * KP, outT, loop ? loop->own : 0.0);
 }
 
 template <typename T>
@@ -252,7 +258,9 @@ struct Tail {
     int op;
     T *outT;            // ALPHA / NORM: the small-matrix outputs
     double *ginv;       // ALPHA: G^-1 for the later BETA step
-    double own;         // NORM: dependence threshold relative to the own diagonal entry
+    LoopCtl *loop;      // CHECK: counts the iteration and may end the inner phase;
+                        // NORM: its dependence threshold `own`
+    const int *gate;    // the kernel returns at once while *gate is set
 };
 
 // SAVE / STORE of the reduced total (tot in LDS, width doubles)
@@ -264,7 +272,11 @@ __device__ void tail_finish(const double *tot, int width, int k, int op, double 
         for (int e = threadIdx.x; e < k * k; e += blockDim.x) vec[e] = tot[(e / k) * KP + e % k];
     }
 }
-// CHECK: tot = squared residual norms
+// CHECK: tot = squared residual norms. With loop control, the decisions of the host
+// loop on the device: at every 4th iteration and at the cap the inner phase ends
+// when every vector has converged, at the cap, or (FP32) after kStallIters
+// iterations, which also switches on the dependence threshold for the rest of the
+// solve.
 template <typename T>
 __device__ void tail_check(const Tail<T> &tl, int k, const double *tot) {
     __shared__ int c;
@@ -276,7 +288,22 @@ __device__ void tail_check(const Tail<T> &tl, int k, const double *tot) {
         if (tot[j] > tl.tol2 * tl.rr0[j]) atomicAdd(&c, 1);
     }
     __syncthreads();
-    if (threadIdx.x == 0) *tl.count = c;
+    if (threadIdx.x == 0) {
+        *tl.count = c;
+        if (LoopCtl *L = tl.loop) {
+            const int it = ++L->it;
+            const bool last = it >= L->max_it;
+            if (last || (it & 3) == 0) {
+                const bool done = last || c == 0;
+                const bool stall = !done && L->stall_ok && it - L->phase0 >= kStallIters;
+                if (stall) {
+                    L->own = kOwnFp32;
+                    L->stall_ok = 0;
+                }
+                if (done || stall) L->gate = 1;
+            }
+        }
+    }
 }
 
 // ------------------------------------------------------------------ kernels
@@ -346,6 +373,7 @@ __global__ __launch_bounds__(kLapGramThreads) void k_lap_gram(long long n, int k
                                                        const int *__restrict__ edeg, const float *__restrict__ P,
                                                        float *__restrict__ Q, int root, const float *__restrict__ R,
                                                        Tail<float> tl) {
+    if (tl.gate && *tl.gate) return;
     constexpr int NT = kLapGramThreads, G = NT / KP, NIT = LapShape<KP>::NIT, RPB = G * NIT;
     constexpr int KK = KP * KP;
     using L = LapTile<float, KP, E>;
@@ -618,6 +646,7 @@ template <int KP>
 __global__ __launch_bounds__(kThreads) void k_mf_rupdate(long long n, int k, const float *__restrict__ negalpha,
                                                          const float *__restrict__ Q, float *__restrict__ R,
                                                          Tail<float> tl) {
+    if (tl.gate && *tl.gate) return;
     constexpr int ROWS = MF<KP>::ROWS;
     __shared__ float sA[4][ROWS * (KP + 1)];
     __shared__ double sn[4][KP];
@@ -659,6 +688,7 @@ template <int KP, int NT>
 __global__ __launch_bounds__(NT) void k_mf_pupdate(long long n, int k, const float *__restrict__ alpha,
                                                    const float *__restrict__ beta, const float *__restrict__ Z,
                                                    float *__restrict__ P, float *__restrict__ X, Tail<float> tl) {
+    if (tl.gate && *tl.gate) return;
     constexpr int ROWS = MF<KP>::ROWS;
     constexpr int NW = NT / 64;
     __shared__ float sA[NW][ROWS * (KP + 1)];
@@ -694,7 +724,7 @@ __global__ __launch_bounds__(NT) void k_mf_pupdate(long long n, int k, const flo
     gram.flush(s_w, tl.part + (long long)blockIdx.x * KK);
     if (tail_reduce(tl.part, gridDim.x, KK, tl.cnt, s_w)) {
         if (tl.op == TAIL_NORM)
-            small_op<float, KP, SM_NORM, NT>(k, s_w, tl.ginv, tl.outT, tl.own);
+            small_op<float, KP, SM_NORM, NT>(k, s_w, tl.ginv, tl.outT, tl.loop ? tl.loop->own : 0.0);
         else
             tail_finish<KP>(s_w, KK, k, tl.op, tl.vec);
     }
@@ -704,7 +734,9 @@ __global__ __launch_bounds__(NT) void k_mf_pupdate(long long n, int k, const flo
 // wave stages its rows of In before it stores them)
 template <int KP, bool ADD>
 __global__ __launch_bounds__(kThreads) void k_mf_rowmul(long long n, int k, const float *__restrict__ M,
-                                                        const float *In, const float *C, float *Out) {
+                                                        const float *In, const float *C, float *Out,
+                                                        const int *__restrict__ gate) {
+    if (gate && *gate) return;
     constexpr int ROWS = MF<KP>::ROWS;
     __shared__ float sA[4][ROWS * (KP + 1)];
     const int w = threadIdx.x >> 6;
@@ -865,23 +897,27 @@ static void launch_gram(const Dims &d, const T *A, const T *B, const T *C, const
 }
 // Q = L_P P, then P'Q and P'R: fused for FP32 blocks of 16 or 32 vectors, else a
 // product pass and a Gram pass
+// one resident wave of product blocks (each walks a range of tiles): more would
+// leave a second, partial wave behind
+template <int KP>
+static int lap_gram_resident() {
+    static const int resident = [] {
+        int dev = 0, cus = 0, per = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_lap_gram<KP, kEllP>, kLapGramThreads, 0) != hipSuccess)
+            return kLapGramBlocks;
+        return std::max(8, std::min(kLapGramBlocks, cus * per / 8 * 8));
+    }();
+    return resident;
+}
 template <typename T, int KP>
 static void launch_lap_gram(Topo &t, Vecs<T> &v, const Dims &d, int root, const Tail<T> &tl, hipStream_t s) {
     if constexpr (UseMF<T, KP>::value) {
         constexpr long long RPB = (kLapGramThreads / KP) * LapShape<KP>::NIT;
-        // one resident wave of blocks (each walks a range of tiles): more would
-        // leave a second, partial wave behind
-        static const int resident = [] {
-            int dev = 0, cus = 0, per = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_lap_gram<KP, kEllP>, kLapGramThreads, 0) != hipSuccess)
-                return kLapGramBlocks;
-            return std::max(8, std::min(kLapGramBlocks, cus * per / 8 * 8));
-        }();
-        const int nb = (int)std::min<long long>(resident, xcd_grid(div_up(d.n, RPB)));
+        const int nb = (int)std::min<long long>(lap_gram_resident<KP>(), xcd_grid(div_up(d.n, RPB)));
         ProfScope ps(PK_SPMM_P, 4.0 * (d.n + 1) + (double)d.p_nnz * (4 + sizeof(T)) + 3.0 * d.n * d.k * sizeof(T), s);
-        lap_long<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, s);
+        lap_long<T>(d, t.prow, t.pcol, v.pval, v.ep, v.p, s, tl.gate);
         hipLaunchKernelGGL((k_lap_gram<KP, kEllP>), dim3(nb), dim3(kLapGramThreads), 0, s, d.n, d.k, t.prow, t.pcol, v.pval,
                            v.ep.tail, v.ep.col, v.ep.val, v.ep.deg, v.p, v.q, root, v.r, tl);
     } else {
@@ -906,9 +942,9 @@ static Tail<T> save_tail(Vecs<T> &v, const Dims &d) {
     return tl;
 }
 template <typename T, int KP, int OP>
-static void launch_small(const Dims &d, Vecs<T> &v, hipStream_t s, double own = 0.0) {
+static void launch_small(const Dims &d, Vecs<T> &v, hipStream_t s, const LoopCtl *loop = nullptr) {
     ProfScope ps(PK_SMALL, 0.0, s);
-    hipLaunchKernelGGL((k_small<T, KP, OP>), dim3(1), dim3(kThreads), 0, s, d.k, v.small, v.smallT, own);
+    hipLaunchKernelGGL((k_small<T, KP, OP>), dim3(1), dim3(kThreads), 0, s, d.k, v.small, v.smallT, loop);
 }
 
 // R -= Q alpha and the convergence count
@@ -927,14 +963,15 @@ static void launch_rupdate(const Dims &d, Vecs<T> &v, Tail<T> tl, hipStream_t s)
 // X += P alpha, P = Z + P beta and the Gram of the new P (with MFMA also rinv from
 // it, in the block that completes the Gram)
 template <typename T, int KP>
-static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s, double own) {
+static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s, const int *gate) {
     const int KK = KP * KP;
     ProfScope ps(PK_PUPDATE, 5.0 * d.n * d.k * sizeof(T), s);
     Tail<T> tl = save_tail(v, d);
     if constexpr (UseMF<T, KP>::value) {
         tl.op = TAIL_NORM;
         tl.outT = v.smallT;
-        tl.own = own;
+        tl.loop = v.loop;
+        tl.gate = gate;
     }
     if constexpr (UseMF<T, KP>::value)
         hipLaunchKernelGGL((k_mf_pupdate<KP, 512>), dim3(kMfGramBlocks), dim3(512), 0, s, d.n, d.k,
@@ -945,11 +982,12 @@ static void launch_pupdate(const Dims &d, Vecs<T> &v, hipStream_t s, double own)
 }
 // Out = (ADD ? C : 0) + In M
 template <typename T, int KP, bool ADD>
-static void launch_rowmul(const Dims &d, const T *M, const T *In, const T *C, T *Out, hipStream_t s) {
+static void launch_rowmul(const Dims &d, const T *M, const T *In, const T *C, T *Out, hipStream_t s,
+                          const int *gate = nullptr) {
     ProfScope ps(PK_ROWMUL, (ADD ? 3.0 : 2.0) * d.n * d.k * sizeof(T), s);
     if constexpr (UseMF<T, KP>::value)
         hipLaunchKernelGGL((k_mf_rowmul<KP, ADD>), dim3(mf_blocks<KP>(d)), dim3(kThreads), 0, s, d.n, d.k, M, In, C,
-                           Out);
+                           Out, gate);
     else
         hipLaunchKernelGGL((k_rowmul<T, KP, ADD>), dim3(vec_blocks(d)), dim3(kThreads), 0, s, d.n, d.k, M, In, C,
                            Out);
@@ -985,13 +1023,32 @@ static void basis_back(const Dims &d, Vecs<T> &v, hipStream_t s) {
     GR_CHECK_LAUNCH();
 }
 
+// device-side loop state of a solve, and the start of a new inner phase
+__global__ void k_loop_init(LoopCtl *L, int max_it, int stall_ok) {
+    L->gate = 0;
+    L->it = 0;
+    L->phase0 = 0;
+    L->max_it = max_it;
+    L->stall_ok = stall_ok;
+    L->own = 0.0;
+}
+__global__ void k_loop_phase(LoopCtl *L) {
+    L->phase0 = L->it;
+    L->gate = 0;
+}
+// host copy of the loop state's gate and iteration count
+static void read_loop(const LoopCtl *L, int out[2], hipStream_t s) {
+    static_assert(offsetof(LoopCtl, it) == sizeof(int), "gate and it are read together");
+    GR_HIP(hipMemcpyAsync(out, L, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    GR_HIP(hipStreamSynchronize(s));
+}
+
 template <typename T>
 SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s,
                     const double *b64) {
     const long long nk = d.n * d.k;
     const int root = 0;
     const int KK = d.kp * d.kp;
-    int *cnt = v.active + kMaxK - 1;
     const Tail<T> tsave = save_tail(v, d);
     SolveInfo info;
     fill_i32(v.tcnt, bpcg_counters(d), 0, s);
@@ -1001,12 +1058,14 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     // FP32 working precision: every inner solve runs on an orthonormal basis of the
     // FP64 residual (FP64 keeps the columns apart by itself)
     const bool basis = v.z64 != nullptr;
-    // FP32: an inner phase that runs kStallIters iterations without every column
-    // converging ends there (the FP64 step takes the partial solution), and the rest of
-    // the solve normalises its blocks with the dependence threshold kOwnFp32
     constexpr bool fp32 = std::is_same<T, float>::value;
-    double own = 0.0;
-    long long phase0 = 0;  // iterations before the current inner phase
+    // The loop's decisions are taken on the device (LoopCtl, in the check kernel's
+    // tail): iteration count and cap, the end of an inner phase, and in FP32 the stall
+    // rule: a phase that runs kStallIters iterations without every column converging
+    // ends there (the FP64 step takes the partial solution) and the rest of the solve
+    // normalises its blocks with the dependence threshold kOwnFp32.
+    hipLaunchKernelGGL(k_loop_init, dim3(1), dim3(1), 0, s, v.loop, (int)std::min<long long>(pp.max_it, INT_MAX),
+                       fp32 ? 1 : 0);
     // a fresh search block: P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
     auto start_block = [&]() {
         if (basis) rhs_basis<T>(d, v, s);
@@ -1017,7 +1076,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
                 ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
                 launch_gram<T, KP, 1>(d, v.p, v.p, nullptr, tsave, s);
             }
-            launch_small<T, KP, SM_NORM>(d, v, s, own);
+            launch_small<T, KP, SM_NORM>(d, v, s, v.loop);
             launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
         });
         GR_CHECK_LAUNCH();
@@ -1030,82 +1089,181 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     tcheck.vec = v.red + RED_RR * kMaxK;
     // squared norms of the inner solve's right-hand sides
     tcheck.rr0 = v.red + (basis ? RED_QN : RED_RN) * kMaxK;
-    tcheck.count = cnt;
+    tcheck.count = v.active + kMaxK - 1;
     tcheck.tol2 = pp.itol * pp.itol;
-    long long it = 0;
-    bool fresh = true, checked = false;  // the next FCG step starts a recurrence; resid64 recomputed
-    while (true) {
-        it++;
-        bool stop = false, restart = false;
+    tcheck.loop = v.loop;
+    // One iteration in two halves; the host loop looks between them. With a gate every
+    // kernel returns at once while the inner phase has ended.
+    //   first:  Q = L_P P, P'Q and P'R, alpha (with MFMA in the block that completes the
+    //           Grams), R -= Q alpha and the check
+    //   second: Z = L_T^+ R with Q'Z and beta (MFMA: formed by the down sweep's tiles),
+    //           X += P alpha, P = Z + P beta with its Gram, P = P R^-1
+    auto first_half = [&](const int *gate) {
         KP_DISPATCH(d.kp, {
-            // Q = L_P P, P'Q and P'R, then alpha (with MFMA in the block that completes
-            // the Grams)
+            Tail<T> tc = tcheck;
+            tc.gate = gate;
             if constexpr (UseMF<T, KP>::value) {
                 Tail<T> ta = tsave;
                 ta.op = TAIL_ALPHA;
                 ta.outT = v.smallT;
                 ta.ginv = v.small + (long long)S_GINV * KK;
+                ta.gate = gate;
                 launch_lap_gram<T, KP>(t, v, d, root, ta, s);
             } else {
                 launch_lap_gram<T, KP>(t, v, d, root, tsave, s);
                 launch_small<T, KP, SM_ALPHA>(d, v, s);
             }
-            launch_rupdate<T, KP>(d, v, tcheck, s);
-            GR_CHECK_LAUNCH();
-            const bool last = it >= pp.max_it;
-            if (last || (it & 3) == 0) {
-                const bool done = last || read_i32(cnt, s) == 0;
-                const bool stall = fp32 && !done && own == 0.0 && it - phase0 >= kStallIters;
-                if (done || stall) {
-                    // every vector's recursive residual fell by itol since the inner
-                    // solve started (or the phase stalled): X += P alpha completes
-                    // z ~ L_P^-1 r, which the FP64 flexible-CG step turns into its next
-                    // direction; the inner solve then restarts from the new FP64 residual
-                    if (stall) own = kOwnFp32;
-                    launch_rowmul<T, KP, true>(d, v.smallT + T_ALPHA * KK, v.p, v.dx, v.dx, s);
-                    if (basis) basis_back<T>(d, v, s);
-                    info.resid64 = fcg_outer_step<T>(t, v, d, fresh, s, basis ? v.z64 : nullptr);
-                    fresh = false;
-                    checked = false;
-                    if (info.resid64 <= pp.rtol) {
-                        // the recurrence's residual drifts from b - L_P x by rounding: check
-                        // the recomputed one, and if it misses the target go on from it
-                        // with a fresh recurrence (residual replacement)
-                        info.resid64 = true_residual<T>(t, v, d, b, s, b64);
-                        checked = fresh = true;
-                    }
-                    if (last || info.resid64 <= pp.rtol || info.outer + 1 >= pp.max_repl) stop = true;
-                    else restart = true;
-                }
-            }
-            if (!stop && !restart) {
-                if constexpr (UseMF<T, KP>::value) {
-                    // Z = L_T^+ R with Q'Z and beta formed by the down sweep's tiles
-                    tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s, v.q, tsave.part, tsave.cnt,
-                                  nullptr, v.small + (long long)S_GINV * KK, v.smallT + T_BETA * KK);
-                } else {
-                    tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
-                    {
-                        ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
-                        launch_gram<T, KP, 1>(d, v.q, v.z, nullptr, tsave, s);
-                    }
-                    launch_small<T, KP, SM_BETA>(d, v, s);
-                }
-                launch_pupdate<T, KP>(d, v, s, own);
-                if constexpr (!UseMF<T, KP>::value) launch_small<T, KP, SM_NORM>(d, v, s, own);
-                launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s);
-            }
-            GR_CHECK_LAUNCH();
+            launch_rupdate<T, KP>(d, v, tc, s);
         });
-        if (stop) break;
-        if (restart) {
-            info.outer++;
-            phase0 = it;
-            start_block();
+        GR_CHECK_LAUNCH();
+    };
+    auto second_half = [&](const int *gate) {
+        KP_DISPATCH(d.kp, {
+            if constexpr (UseMF<T, KP>::value) {
+                tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s, v.q, tsave.part, tsave.cnt, nullptr,
+                              v.small + (long long)S_GINV * KK, v.smallT + T_BETA * KK, gate);
+            } else {
+                tree_solve<T>(t, v, d, v.r, v.z, nullptr, nullptr, nullptr, s);
+                {
+                    ProfScope ps(PK_BGRAM, 2.0 * nk * sizeof(T), s);
+                    launch_gram<T, KP, 1>(d, v.q, v.z, nullptr, tsave, s);
+                }
+                launch_small<T, KP, SM_BETA>(d, v, s);
+            }
+            launch_pupdate<T, KP>(d, v, s, gate);
+            if constexpr (!UseMF<T, KP>::value) launch_small<T, KP, SM_NORM>(d, v, s, v.loop);
+            launch_rowmul<T, KP, false>(d, v.smallT + T_RINV * KK, v.p, nullptr, v.p, s, gate);
+        });
+        GR_CHECK_LAUNCH();
+    };
+
+    // Concurrent paths (LaunchSched of the worker thread): chunks of four iterations
+    // captured once per solve as a hipGraph and replayed `chunks` times between host
+    // reads (the fused MFMA kernels only: FP32 at k = 16 or 32, and never while kernels
+    // are timed). Replays past the end of a phase do nothing, so the results are those
+    // of the kernel-by-kernel loop.
+    LaunchSched *sc = g_sched;
+    bool can_capture = sc != nullptr && sc->mode == 1 && fp32 && (d.kp == 16 || d.kp == 32) && s != nullptr &&
+                       !(g_prof != nullptr && g_prof->on);
+    struct GraphHold {
+        hipGraphExec_t exec = nullptr;
+        ~GraphHold() {
+            if (exec) (void)hipGraphExecDestroy(exec);
         }
+    } gh;
+    auto capture = [&]() -> bool {
+        const int *gate = &v.loop->gate;
+        KP_DISPATCH(d.kp, {
+            if constexpr (UseMF<T, KP>::value) (void)lap_gram_resident<KP>();  // host queries stay out of the capture
+        });
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        hipGraph_t g = nullptr;
+        try {
+            for (int i = 0; i < 4; i++) {
+                first_half(gate);
+                second_half(gate);
+            }
+        } catch (...) {
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        if (hipStreamEndCapture(s, &g) != hipSuccess || g == nullptr) {
+            (void)hipGetLastError();
+            return false;
+        }
+        const hipError_t e = hipGraphInstantiate(&gh.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            gh.exec = nullptr;
+            return false;
+        }
+        if (sc->stats) sc->stats->captures++;
+        return true;
+    };
+    const int tkey = Tuner::key(d.n, d.kp);
+    int cand = -1;  // tuner candidate of the current phase
+    auto pick = [&]() -> int {
+        cand = -1;
+        if (!can_capture) return 0;
+        if (sc->chunks > 0) return sc->chunks;
+        if (!sc->tuner) return 4;
+        cand = sc->tuner->pick(tkey);
+        return kSchedCand[cand];
+    };
+    int chunks = pick();
+    auto phase_t0 = std::chrono::steady_clock::now();
+    long long phase_it0 = 0, reads = 0, replays = 0;
+
+    long long it = 0;
+    bool fresh = true, checked = false;  // the next FCG step starts a recurrence; resid64 recomputed
+    while (true) {
+        bool end = false;
+        if (chunks > 0 && can_capture && it + 4 <= pp.max_it) {
+            if (!gh.exec && !capture()) {
+                can_capture = false;
+                chunks = 0;
+                continue;
+            }
+            const int nrep = (int)std::min<long long>(chunks, (pp.max_it - it) / 4);
+            for (int i = 0; i < nrep; i++) GR_HIP(hipGraphLaunch(gh.exec, s));
+            int lc[2];
+            read_loop(v.loop, lc, s);
+            replays += nrep;
+            reads++;
+            end = lc[0] != 0;
+            it = lc[1];
+        } else {
+            it++;
+            first_half(nullptr);
+            if (it >= pp.max_it || (it & 3) == 0) {
+                int lc[2];
+                read_loop(v.loop, lc, s);
+                reads++;
+                end = lc[0] != 0;
+            }
+            if (!end) second_half(nullptr);
+        }
+        if (!end) continue;
+        if (cand >= 0) {
+            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - phase_t0).count();
+            sc->tuner->record(tkey, cand, sec / (double)std::max<long long>(1, it - phase_it0));
+        }
+        // every vector's recursive residual fell by itol since the inner solve started
+        // (or the phase stalled): X += P alpha completes z ~ L_P^-1 r, which the FP64
+        // flexible-CG step turns into its next direction; the inner solve then restarts
+        // from the new FP64 residual
+        KP_DISPATCH(d.kp, { launch_rowmul<T, KP, true>(d, v.smallT + T_ALPHA * KK, v.p, v.dx, v.dx, s); });
+        if (basis) basis_back<T>(d, v, s);
+        info.resid64 = fcg_outer_step<T>(t, v, d, fresh, s, basis ? v.z64 : nullptr);
+        fresh = false;
+        checked = false;
+        if (info.resid64 <= pp.rtol) {
+            // the recurrence's residual drifts from b - L_P x by rounding: check the
+            // recomputed one, and if it misses the target go on from it with a fresh
+            // recurrence (residual replacement)
+            info.resid64 = true_residual<T>(t, v, d, b, s, b64);
+            checked = fresh = true;
+        }
+        if (it >= pp.max_it || info.resid64 <= pp.rtol || info.outer + 1 >= pp.max_repl) break;
+        info.outer++;
+        hipLaunchKernelGGL(k_loop_phase, dim3(1), dim3(1), 0, s, v.loop);
+        start_block();
+        chunks = pick();
+        phase_t0 = std::chrono::steady_clock::now();
+        phase_it0 = it;
     }
     info.outer++;
     info.iters = it;
+    if (sc != nullptr && sc->stats != nullptr) {
+        sc->stats->iterations += it;
+        sc->stats->host_reads += reads;
+        sc->stats->replays += replays;
+    }
     // the reported residual is always the one recomputed from the solution
     if (!checked) info.resid64 = true_residual<T>(t, v, d, b, s, b64);
     return info;

@@ -5,6 +5,7 @@
 
 #include "common.h"
 #include "profiler.h"
+#include "sched.h"
 
 struct grass_ctx {
     int device = 0;
@@ -13,6 +14,12 @@ struct grass_ctx {
     void *own_ws = nullptr;
     size_t own_bytes = 0;
     grass::Profiler prof;
+    // launch schedule of the batch and server workers (grass_set_launch_mode), the
+    // autotuner's choices per size class and the counters of grass_launch_stats_read
+    int launch_mode = 1;
+    int launch_chunks = 0;
+    grass::Tuner tuner;
+    grass::LaunchStats lstats;
 };
 
 namespace grass {

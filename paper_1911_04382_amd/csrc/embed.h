@@ -32,9 +32,10 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
                int root, const unsigned long long *scale_from, double *dot_part, hipStream_t s);
 // The entries past E of the rows longer than kLongRow, one workgroup per row, into
 // ell.tail (lap_apply calls it; callers of the product kernels directly must too).
+// With gate: returns at once while *gate is set.
 template <typename T>
 void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x,
-              hipStream_t s);
+              hipStream_t s, const int *gate = nullptr);
 
 // Grounded tree solve x = L_T^+ y (x[root] = 0): up-sweep then down-sweep over the
 // heavy-light levels. x may alias y. Optional fused outputs of the down-sweep:
@@ -43,6 +44,7 @@ void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, co
 // Q'x (qz_q n x k) from per-tile FP64 partials in qz_part (counters qz_cnt), and the
 // last tile stores the k x k total (row-major, ld kp) at qz_out or, with beta_out,
 // stores beta = -G^-1 Q'x there instead (G^-1 at beta_ginv, both k x k, ld kp).
+// With gate: every kernel of the solve returns at once while *gate is set.
 // y = L_G x64 (grounded nowhere) in FP64, scaled by the power of two from
 // scale_from: the right-hand side of the next L_P solve, kept in FP64.
 void lap_apply_x64(Topo &t, const Dims &d, const double *x64, double *y, const unsigned long long *scale_from,
@@ -51,13 +53,12 @@ template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s, const T *qz_q = nullptr, double *qz_part = nullptr,
                 int *qz_cnt = nullptr, double *qz_out = nullptr, const double *beta_ginv = nullptr,
-                T *beta_out = nullptr);
+                T *beta_out = nullptr, const int *gate = nullptr);
 
-// L_P solve: block PCG in working precision with the tree preconditioner, refined
-// in FP64: whenever every vector's recursive residual has fallen by
-// pcg_inner_rtol, the correction moves into the FP64 solution, the residual is
-// recomputed in FP64 and the block PCG restarts from it. (Keeping the search block
-// across the replacement instead diverged on ill-conditioned meshes in FP32.)
+// L_P solve: block PCG in working precision with the tree preconditioner inside an
+// FP64 flexible CG: whenever every vector's recursive residual has fallen by
+// pcg_inner_rtol, the block PCG's solution becomes the next FP64 search direction
+// and the block PCG restarts from the new FP64 residual (bpcg.hip).
 // Ends when ||b - L_P x||_2 <= pcg_rtol ||b||_2 per vector (FP64). Returns the
 // iterations, the FP64 relative residual and the number of restarts.
 struct SolveInfo {

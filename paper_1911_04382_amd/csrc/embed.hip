@@ -623,7 +623,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_sweep(
     const int *__restrict__ dep, int *__restrict__ ticket, unsigned *__restrict__ devflags,
     const T *__restrict__ rdot, double *__restrict__ dot_part, unsigned long long *__restrict__ absmax,
     const T *__restrict__ qz_q, double *__restrict__ qz_part, int *__restrict__ qz_cnt, double *__restrict__ qz_out,
-    const double *__restrict__ beta_ginv, T *__restrict__ beta_out) {
+    const double *__restrict__ beta_ginv, T *__restrict__ beta_out, const int *__restrict__ gate) {
+    if (gate && *gate) return;
     __shared__ int s_tk;
     if (threadIdx.x == 0) s_tk = atomicAdd(ticket, 1);
     __syncthreads();
@@ -636,7 +637,8 @@ __global__ __launch_bounds__(kSolveThreads) void k_sweep(
 
 // start of a solve: reset the sweep tickets and advance the device-side epoch by
 // two (one per sweep), so stamps of earlier solves never match
-__global__ void k_solve_begin(int *__restrict__ tickets, unsigned *__restrict__ epoch) {
+__global__ void k_solve_begin(int *__restrict__ tickets, unsigned *__restrict__ epoch, const int *__restrict__ gate) {
+    if (gate && *gate) return;
     if (threadIdx.x == 0) {
         tickets[0] = 0;
         tickets[1] = 0;
@@ -1333,6 +1335,7 @@ void plan_vecs(Arena &a, const Dims &d, Vecs<T> &v) {
     v.tcnt = a.take<int>(bpcg_counters(d));
     v.red = a.take<double>(RED_SLOTS * kMaxK);
     v.active = a.take<int>(kMaxK);
+    v.loop = a.take<LoopCtl>(1);
     v.u64s = a.take<unsigned long long>(U_SLOTS);
 }
 
@@ -1353,11 +1356,11 @@ void start_vectors(const Dims &d, uint64_t seed, int pass, T *out, Vecs<T> &v, h
 
 template <typename T>
 void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, const Ell<T> &ell, const T *x,
-              hipStream_t s) {
+              hipStream_t s, const int *gate) {
     if (ell.nlong == 0) return;
     KP_DISPATCH(d.kp, {
         hipLaunchKernelGGL((k_lap_long<T, KP>), dim3(ell.nlong), dim3(kThreads), 0, s, d.k, ell.E, rowptr, col, val,
-                           ell.lrow, x, ell.tail);
+                           ell.lrow, x, ell.tail, gate);
     });
     GR_CHECK_LAUNCH();
 }
@@ -1413,13 +1416,13 @@ void lap_apply_x64(Topo &t, const Dims &d, const double *x64, double *y, const u
 template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s, const T *qz_q, double *qz_part, int *qz_cnt,
-                double *qz_out, const double *beta_ginv, T *beta_out) {
+                double *qz_out, const double *beta_ginv, T *beta_out, const int *gate) {
     const int nt = (int)t.ntiles_used;
     const double vbytes = 2.0 * d.n * d.k * sizeof(T);
-    hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(64), 0, s, t.tickets, t.epoch_dev);
+    hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(64), 0, s, t.tickets, t.epoch_dev, gate);
 #define SWEEP_ARGS(TK, DP, DEP, RD, DOT, AM, QQ, QP, QC, QO, BG, BO)                                            \
     nt, t.nlev, t.lvl_tile, d.k, t.perm, t.flags, t.ptop, t.lc_ptr, t.lc_pos, t.lc_owner, v.rpw, y, v.F, x,        \
-        v.aggw, t.done, t.epoch_dev, DP, DEP, TK, t.devflags, RD, DOT, AM, QQ, QP, QC, QO, BG, BO
+        v.aggw, t.done, t.epoch_dev, DP, DEP, TK, t.devflags, RD, DOT, AM, QQ, QP, QC, QO, BG, BO, gate
     KP_DISPATCH(d.kp, {
         {
             // y in, subtree sums out; per node: flags, perm, light-child pointers
@@ -1664,13 +1667,13 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
     template void plan_vecs<T>(Arena &, const Dims &, Vecs<T> &);                                                \
     template void start_vectors<T>(const Dims &, uint64_t, int, T *, Vecs<T> &, hipStream_t);                    \
     template void lap_long<T>(const Dims &, const int *, const int *, const T *, const Ell<T> &, const T *,       \
-                              hipStream_t);                                                                   \
+                              hipStream_t, const int *);                                                      \
     template void lap_apply<T>(const Dims &, const int *, const int *, const T *, const Ell<T> &, const T *, T *, \
                                int,                                                                              \
                                const unsigned long long *, double *, hipStream_t);                               \
     template void tree_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const T *, double *,            \
                                 unsigned long long *, hipStream_t, const T *, double *, int *, double *,         \
-                                const double *, T *);                                                            \
+                                const double *, T *, const int *);                                               \
     template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, hipStream_t, const double *);  \
     template double fcg_outer_step<T>(Topo &, Vecs<T> &, const Dims &, bool, hipStream_t, const double *);        \
     template SolveInfo pcg_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const grass_opts &,         \

@@ -284,7 +284,8 @@ template <typename T, int KP>
 __global__ __launch_bounds__(kThreads) void k_lap_long(int k, int E, const int *__restrict__ rowptr,
                                                        const int *__restrict__ col, const T *__restrict__ val,
                                                        const int *__restrict__ lrow, const T *__restrict__ x,
-                                                       T *__restrict__ tail) {
+                                                       T *__restrict__ tail, const int *__restrict__ gate = nullptr) {
+    if (gate && *gate) return;
     constexpr int G = kThreads / KP, U = 4;
     __shared__ T s[G][KP];
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;

@@ -132,6 +132,12 @@ struct grass_server {
     void worker(int w) {
         (void)hipSetDevice(device);
         grass::g_prof = nullptr;
+        grass::LaunchSched sched;
+        sched.mode = ctx->launch_mode;
+        sched.chunks = ctx->launch_chunks;
+        sched.tuner = &ctx->tuner;
+        sched.stats = &ctx->lstats;
+        grass::g_sched = &sched;
         std::unique_lock<std::mutex> lk(mu);
         while (true) {
             grass::Request *r = nullptr;
@@ -160,6 +166,7 @@ struct grass_server {
             cv_done.notify_all();
             cv_work.notify_all();
         }
+        grass::g_sched = nullptr;
     }
 };
 
@@ -228,6 +235,12 @@ grass_status grass_sparsify_batch(grass_ctx *ctx, int32_t count, const grass_gra
                 local.on = prof_on;
                 local.mask = prof_mask;
                 g_prof = prof_on ? &local : nullptr;
+                LaunchSched sched;
+                sched.mode = ctx->launch_mode;
+                sched.chunks = ctx->launch_chunks;
+                sched.tuner = &ctx->tuner;
+                sched.stats = &ctx->lstats;
+                g_sched = &sched;
                 char *slice = static_cast<char *>(workspace) + slot * (size_t)w;
                 for (int i; (i = next.fetch_add(1)) < count;) {
                     const int idx = order[i];
@@ -248,6 +261,7 @@ grass_status grass_sparsify_batch(grass_ctx *ctx, int32_t count, const grass_gra
                 }
                 if (prof_on) merge_profile(ctx->prof, local, mu);
                 g_prof = nullptr;
+                g_sched = nullptr;
             });
         }
         for (auto &th : threads) th.join();

@@ -109,6 +109,21 @@ constexpr int kEllG = 8;  // 7-point meshes and grids fit whole rows
 constexpr int kEllP = 4;  // spanning tree plus a few edges
 constexpr int kLongRow = 32;  // rows longer than this get a workgroup of their own
 
+// Device-side control of the block PCG's inner loop (one per solve): the check
+// kernel's tail counts the iteration and, where the host loop would look (every 4th
+// iteration and the last), decides whether the inner phase ends (gate = 1). Kernels
+// launched with a gate return at once while it is set, so a captured chunk of
+// iterations replayed past the end does nothing.
+struct LoopCtl {
+    int gate;      // 1: the inner phase has ended
+    int it;        // iterations so far in this solve
+    int phase0;    // iterations before the current inner phase
+    int max_it;    // iteration cap of the solve
+    int stall_ok;  // a stall may still switch on the dependence threshold (FP32)
+    int pad[3];
+    double own;    // dependence threshold of the block normalisation (0: off)
+};
+
 // Precision-dependent buffers.
 template <typename T>
 struct Vecs {
@@ -136,6 +151,7 @@ struct Vecs {
     int *tcnt = nullptr;      // their arrival counters (zero between launches)
     double *red = nullptr;    // [16*kMaxK] reduced vectors (num, den, rz, pq, rr, rr0, bnorm, ...)
     int *active = nullptr;    // [kMaxK] PCG column flags + count at [kMaxK-1]
+    LoopCtl *loop = nullptr;  // inner-loop control of the block PCG
     unsigned long long *u64s = nullptr;  // [8]: heat max bits, lambda_min bits, absmax bits
 };
 

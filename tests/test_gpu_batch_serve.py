@@ -101,6 +101,81 @@ def test_batch_fp64_matches_oracle(ctx):
         np.testing.assert_allclose(r.scores.cpu().numpy(), ref.scores, atol=1e-10)
 
 
+def fused_set():
+    """Graphs whose L_P solves take the fused MFMA block PCG (FP32, k = 16 or 32)."""
+    return [
+        # stalls once in its first densified pass at k = 32: the stall rule runs in the
+        # check kernel's tail
+        (G.mesh3d(42, 42, 42, (G.W_UNIFORM, 1.0, 10.0), seed=7), 32),
+        (G.grid2d(120, 110, seed=11), 16),
+        (G.rgg(20000, seed=12), 16),
+        (G.mesh3d(20, 20, 20, weights=(G.W_LOGUNIFORM10, -3, 3), seed=13), 32),
+        (G.ba(6000, seed=14), 16),
+    ]
+
+
+@pytest.fixture(scope="module")
+def alone_fused(ctx):
+    items = fused_set()
+    dgs = [grass.to_device(g, DEV) for g, _ in items]
+    opts = [grass.make_opts(k=k, t=2, precision=32, seed=5, sigma2=100.0) for _, k in items]
+    res = [grass.grass_sparsify(ctx, dg, o) for dg, o in zip(dgs, opts)]
+    torch.cuda.synchronize()
+    return dgs, opts, res
+
+
+@pytest.mark.parametrize("chunks", [1, 3, 8, 0])
+def test_captured_batch_equals_alone(ctx, alone_fused, chunks):
+    """The batch through the captured schedule: chunks of four block-PCG iterations
+    captured as a hipGraph and replayed `chunks` times between host reads (0: chosen
+    by the context's autotuner), the loop decided on the device. Every output, the
+    iteration counts included, is bit for bit the kernel-by-kernel single-graph one."""
+    dgs, opts, ref = alone_fused
+    ctx.set_launch_mode(grass.LAUNCH_CAPTURED, chunks)
+    try:
+        ctx.launch_stats(reset=True)
+        say("captured batch, chunks per read", chunks)
+        rc, out = grass.grass_sparsify_batch(ctx, dgs, opts, workers=3)
+        st = ctx.launch_stats()
+    finally:
+        ctx.set_launch_mode(grass.LAUNCH_CAPTURED, 0)
+    say("  ", st)
+    assert rc == grass.OK
+    for a, b in zip(out, ref):
+        same(a, b)
+    assert st["iterations"] == sum(r.summary["pcg_iters"] for r in ref)
+    assert st["captures"] > 0 and st["graph_replays"] > 0
+    if chunks >= 3:
+        # one read per `chunks` replays of four iterations, plus the phase ends
+        assert st["host_reads"] * 4 < st["iterations"] / 2
+
+
+def test_kernel_by_kernel_batch_equals_alone(ctx, alone_fused):
+    """GRASS_LAUNCH_KERNELS: no capture; the host reads the device's loop state every
+    4th iteration, and the outputs are again those of the single-graph path."""
+    dgs, opts, ref = alone_fused
+    ctx.set_launch_mode(grass.LAUNCH_KERNELS, 0)
+    try:
+        ctx.launch_stats(reset=True)
+        rc, out = grass.grass_sparsify_batch(ctx, dgs, opts, workers=2)
+        st = ctx.launch_stats()
+    finally:
+        ctx.set_launch_mode(grass.LAUNCH_CAPTURED, 0)
+    say("  ", st)
+    assert rc == grass.OK
+    for a, b in zip(out, ref):
+        same(a, b)
+    assert st["captures"] == 0 and st["graph_replays"] == 0
+    assert st["host_reads"] >= st["iterations"] // 4
+
+
+def test_launch_mode_rejects_bad_arguments(ctx):
+    with pytest.raises(grass.GrassError):
+        ctx.set_launch_mode(7, 0)
+    with pytest.raises(grass.GrassError):
+        ctx.set_launch_mode(grass.LAUNCH_CAPTURED, 65)
+
+
 def test_server_alone_and_in_the_mix(ctx, alone):
     gs, dgs, opts, ref = alone
     need = [grass.load_library().grass_workspace_bytes(dg.n, dg.m, opts) for dg in dgs]
