@@ -210,9 +210,11 @@ def percentile(xs, q):
 
 def run_batch(args, grass, torch):
     """C4: many independent graphs. The plain path sparsifies them one after another
-    on one stream; grass_sparsify_batch runs `workers` at once."""
+    on one stream; grass_sparsify_batch runs `workers` at once, kernel by kernel or
+    with captured block-PCG chunks and loop control on the device."""
     from paper_1911_04382_amd import graphs as G
 
+    legs = set(args.c4_legs.split(","))
     sizes = G.config_c4_sizes(256)[: args.count]
     gs = [G.config_c4_graph(kind, n, seed=i) for i, (kind, n) in enumerate(sizes)]
     dgs = [grass.to_device(g, "cuda:0") for g in gs]
@@ -220,14 +222,16 @@ def run_batch(args, grass, torch):
     ctx = grass.Context(0)
     torch.cuda.synchronize()
     log(f"C4: {len(gs)} graphs, {sum(g.n for g in gs)} nodes, {sum(g.m for g in gs)} edges")
-    t0 = time.perf_counter()
-    plain = []
-    for i, dg in enumerate(dgs):
-        plain.append(grass.grass_sparsify(ctx, dg, opts))  # returns when the graph is done
-        if (i + 1) % 8 == 0:
-            log(f"plain path: {i + 1}/{len(dgs)} graphs at {time.perf_counter() - t0:.1f} s")
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
+    plain, t_plain = None, None
+    if "plain" in legs:
+        t0 = time.perf_counter()
+        plain = []
+        for i, dg in enumerate(dgs):
+            plain.append(grass.grass_sparsify(ctx, dg, opts))  # returns when the graph is done
+            if (i + 1) % 8 == 0:
+                log(f"plain path: {i + 1}/{len(dgs)} graphs at {time.perf_counter() - t0:.1f} s")
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
     ws = grass.batch_workspace(dgs, opts, args.workers)
 
     def batch(mode, label):
@@ -240,27 +244,40 @@ def run_batch(args, grass, torch):
         dt = time.perf_counter() - t0
         st = ctx.launch_stats()
         log(f"batch path ({label}): done in {dt:.1f} s, {st}")
-        same = all(torch.equal(a.mask, b.mask) and torch.equal(a.scores, b.scores) for a, b in zip(out, plain))
+        same = None if plain is None else all(
+            torch.equal(a.mask, b.mask) and torch.equal(a.scores, b.scores) for a, b in zip(out, plain))
         return dt, out, same, st
 
-    # worker pool, kernel by kernel (host reads the loop state every 4th iteration)
-    t_kern, _, same_kern, st_kern = batch(grass.LAUNCH_KERNELS, "kernel by kernel")
-    # worker pool with captured chunks and device-side loop control; the first run
-    # also tunes chunks per read for each size class, the second reuses the choices
-    t_cold, _, same_cold, st_cold = batch(grass.LAUNCH_CAPTURED, "captured, tuning")
-    t_batch, out, same, st = batch(grass.LAUNCH_CAPTURED, "captured, tuned")
-    same = same and same_kern and same_cold
+    runs = {}
+    if "kernels" in legs:
+        # worker pool, kernel by kernel (the host reads the loop state every 4th iteration)
+        runs["kernels"] = batch(grass.LAUNCH_KERNELS, "kernel by kernel")
+    if "captured" in legs:
+        # captured chunks, loop control on the device; the first run also tunes the
+        # chunks per read of each size class, the second reuses the choices
+        runs["captured_tuning"] = batch(grass.LAUNCH_CAPTURED, "captured, tuning")
+        runs["captured"] = batch(grass.LAUNCH_CAPTURED, "captured, tuned")
+    key = "captured" if "captured" in runs else ("kernels" if "kernels" in runs else None)
+    if key is None:
+        ctx.close()
+        print(json.dumps({"metric": "off-tree edges scored/sec, batch of independent graphs", "plain_s": t_plain}),
+              flush=True)
+        return
+    t_batch, out, _, _ = runs[key]
+    sames = [r[2] for r in runs.values() if r[2] is not None]
     scored = sum(r.summary["scored_edges"] for r in out)
     line = {"metric": "off-tree edges scored/sec, batch of independent graphs", "value": scored / t_batch,
             "unit": "edges/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"C4: first {len(gs)} of 256 graphs cycling 2D mesh / 3D mesh / RGG, n log-uniform "
                                    "[1e3, 2e5], U[1,10), k=16, t=2, sigma^2=100",
                        "graphs": len(gs), "nodes": sum(g.n for g in gs), "workers": args.workers,
-                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
-            "batch_s": t_batch, "batch_tuning_s": t_cold, "batch_kernels_s": t_kern, "plain_s": t_plain,
-            "plain_value": scored / t_plain, "speedup": t_plain / t_batch, "speedup_vs_kernels": t_kern / t_batch,
-            "launch_stats": {"captured": st, "captured_tuning": st_cold, "kernels": st_kern},
-            "identical_to_plain": same,
+                       "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES"), "launch": key},
+            "batch_s": t_batch, "plain_s": t_plain,
+            "runs_s": {k: r[0] for k, r in runs.items()},
+            "launch_stats": {k: r[3] for k, r in runs.items()},
+            "plain_value": scored / t_plain if t_plain else None,
+            "speedup": t_plain / t_batch if t_plain else None,
+            "identical_to_plain": all(sames) if sames else None,
             "statuses": {str(k): sum(1 for r in out if r.status == k) for k in sorted({r.status for r in out})}}
     ctx.close()
     print(json.dumps(line), flush=True)
@@ -532,7 +549,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain device copy of known size (PMC calibration)")
     ap.add_argument("--count", type=int, default=256, help="c4: graphs; c5: requests")
-    ap.add_argument("--workers", type=int, default=8, help="c4/c5: concurrent graphs")
+    ap.add_argument("--workers", type=int, default=None, help="c4/c5: concurrent graphs [c4: 16, else 8]")
+    ap.add_argument("--c4-legs", default="plain,kernels,captured",
+                    help="c4: which runs to make (plain = one graph per call; kernels / captured = the batch with "
+                         "that launch schedule, captured twice: tuning, then tuned)")
     ap.add_argument("--rho", type=float, default=0.7, help="c5: arrival rate / plain-path capacity")
     ap.add_argument("--c5-max-n", type=float, default=2e6, help="c5: largest request (nodes)")
     ap.add_argument("--arena-gb", type=float, default=16.0, help="c5: server arena (GiB)")
@@ -541,6 +561,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="default run: skip the served-stream leg, the oracle accuracy check and the true kappa")
     args = ap.parse_args()
+    if args.workers is None:
+        args.workers = 16 if args.workload == "c4" else 8
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build runs a single graph (or batch) per device and has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)

@@ -1198,6 +1198,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     int chunks = pick();
     auto phase_t0 = std::chrono::steady_clock::now();
     long long phase_it0 = 0, reads = 0, replays = 0;
+    long long prev_len = 0;  // length of the solve's previous inner phase (0: none yet)
 
     long long it = 0;
     bool fresh = true, checked = false;  // the next FCG step starts a recurrence; resid64 recomputed
@@ -1209,7 +1210,12 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
                 chunks = 0;
                 continue;
             }
-            const int nrep = (int)std::min<long long>(chunks, (pp.max_it - it) / 4);
+            // up to `chunks` replays, but not past the end that the previous phase's
+            // length predicts (then one at a time): replays after the end do nothing
+            // but still take launch slots that other graphs' kernels could use
+            long long want = chunks;
+            if (prev_len > 0) want = std::max<long long>(1, std::min<long long>(chunks, (prev_len - (it - phase_it0)) / 4));
+            const int nrep = (int)std::min<long long>(want, (pp.max_it - it) / 4);
             for (int i = 0; i < nrep; i++) GR_HIP(hipGraphLaunch(gh.exec, s));
             int lc[2];
             read_loop(v.loop, lc, s);
@@ -1254,6 +1260,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
         hipLaunchKernelGGL(k_loop_phase, dim3(1), dim3(1), 0, s, v.loop);
         start_block();
         chunks = pick();
+        prev_len = it - phase_it0;
         phase_t0 = std::chrono::steady_clock::now();
         phase_it0 = it;
     }
