@@ -838,7 +838,7 @@ grass_status grass_profile_enable(grass_ctx *ctx, uint32_t kinds) {
 int32_t grass_profile_read(const grass_ctx *ctx, grass_kernel_stats *out, int32_t cap) {
     static const char *names[PK_COUNT] = {"spmm_LG",  "spmm_LP",   "tree_up", "tree_down", "score",
                                           "gram_PQR", "r_update",  "gram_QZ", "p_update",  "p_normalize", "pcg_small",
-                                          "resid64",  "start_vectors", "select"};
+                                          "resid64",  "start_vectors", "select", "spmm_LG64"};
     if (!ctx) return 0;
     int32_t n = 0;
     for (int i = 0; i < PK_COUNT && n < cap; i++) {

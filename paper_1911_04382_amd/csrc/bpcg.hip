@@ -834,27 +834,32 @@ __global__ __launch_bounds__(kThreads) void k_rhs_basis(int k, const double *__r
     if (tid < kMaxK) qn[tid] = (tid < k && live[tid]) ? 1.0 : 0.0;
 }
 
-// out = in M for an upper-triangular k x k M (FP64, ld KP), row by row in FP64
+// out = in M for an upper-triangular k x k M (FP64, ld KP), row by row in FP64: a
+// lane group stages its row in LDS (one coalesced load per value) and each lane
+// sums its column from there
 template <typename TI, typename TO, int KP>
 __global__ __launch_bounds__(kThreads) void k_basis_map(long long n, int k, const TI *__restrict__ in,
                                                         const double *__restrict__ M, TO *__restrict__ out, int nblk) {
     constexpr int G = kThreads / KP;
     constexpr int RPB = G * kRowsPerGroup;
+    static_assert(KP <= 64, "a lane group within one wave");
     __shared__ double sm[KP * KP];
+    __shared__ double srow[G][KP];
     const int bid = xcd_block(blockIdx.x, gridDim.x);
     if (bid >= nblk) return;  // whole block
     for (int e = threadIdx.x; e < KP * KP; e += kThreads) sm[e] = M[e];
     __syncthreads();
     const int g = threadIdx.x / KP, j = threadIdx.x % KP;
-    if (j >= k) return;
     const long long r0 = (long long)bid * RPB;
-    for (int i = g; i < RPB; i += G) {
+    for (int i = g; i < RPB; i += G) {  // the same trip count in every lane of a group
         const long long v = r0 + i;
         if (v >= n) break;
-        const TI *row = in + v * k;
+        srow[g][j] = j < k ? (double)in[v * k + j] : 0.0;
+        __builtin_amdgcn_wave_barrier();  // the group's writes are seen by its reads (one wave)
         double acc = 0.0;
-        for (int l = 0; l <= j; l++) acc += (double)row[l] * sm[l * KP + j];
-        out[v * k + j] = (TO)acc;
+        for (int l = 0; l <= j; l++) acc += srow[g][l] * sm[l * KP + j];
+        if (j < k) out[v * k + j] = (TO)acc;
+        __builtin_amdgcn_wave_barrier();  // the group's reads are done before the next row
     }
 }
 

@@ -1405,7 +1405,7 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
 void lap_apply_x64(Topo &t, const Dims &d, const double *x64, double *y, const unsigned long long *scale_from,
                    hipStream_t s) {
     const int nbv = vec_blocks(d);
-    ProfScope ps(PK_SPMM_G, 4.0 * (d.n + 1) + 2.0 * d.m * 16 + (double)d.n * d.k * 16, s);
+    ProfScope ps(PK_SPMM_G64, 4.0 * (d.n + 1) + 2.0 * d.m * 16 + (double)d.n * d.k * 16, s);
     KP_DISPATCH(d.kp, {
         hipLaunchKernelGGL((k_lap_x64<double, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.rowptr,
                            t.col, t.ceid, t.w, x64, y, scale_from, nbv);

@@ -19,6 +19,7 @@ enum ProfKind : int {
     PK_RESID64,     // FP64 outer iteration: residual, flexible-CG step, right-hand-side basis
     PK_START,       // start vectors
     PK_SELECT,      // candidate filter, sort and greedy
+    PK_SPMM_G64,    // y = L_G x64 in FP64 (k_lap_x64): the right-hand side after an L_P solve
     PK_COUNT
 };
 
