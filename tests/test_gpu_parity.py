@@ -195,6 +195,42 @@ def test_embed_with_added_edges_pcg(ctx, case):
     assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
 
 
+# a seeded sample of 16 of the 256 graphs of the mixed-size batch (2-D meshes, 3-D
+# meshes, random geometric graphs; U[1,10), k = 16, t = 2, FP32)
+C4_SAMPLE = sorted(int(i) for i in np.random.default_rng(4).choice(256, 16, replace=False))
+C4_ORACLE_MAX_N = 40000  # larger graphs take the oracle's PCG too long for a test
+
+
+@pytest.mark.parametrize("idx", C4_SAMPLE)
+def test_c4_sample_tree_and_pcg_pass(ctx, idx):
+    """One graph of the mixed-size batch, as the batch runs it: the tree pass and the
+    first densified pass (the oracle's own P after its tree pass, solved by the FP32
+    block PCG) against the oracle, at the FP32 bar."""
+    kind, n = G.config_c4_sizes(256)[idx]
+    g = G.config_c4_graph(kind, n, seed=idx)
+    if g.n > C4_ORACLE_MAX_N:
+        pytest.skip(f"graph {idx} ({kind}, {g.n} nodes) is beyond the oracle's test budget")
+    say(f"C4 graph {idx}: {kind}", g.n, g.m)
+    k, t = 16, 2
+    tmask = O.max_spanning_tree(g)
+    dg = grass.to_device(g, DEV)
+    opts = grass.make_opts(k=k, t=t, precision=32, seed=0, sigma2=100.0)
+    heat, st = grass.grass_embed(ctx, dg, torch.as_tensor(tmask).to(DEV), opts, pass_=0)
+    r0 = O.embed(g, tmask, k=k, t=t, seed=0)
+    _fp32_bar(heat.cpu().numpy().astype(np.float64), r0.heat, tmask == 0, _cutoff(g, tmask, r0, 100.0, t))
+    assert st["lambda_max"] == pytest.approx(r0.stats["lambda_max"], rel=1e-4)
+    th = O.theta(100.0, r0.stats["lambda_min"], r0.stats["lambda_max"], t)
+    P, acc, _ = O.filter_select(g, r0.heat, tmask, th, r0.stats["heat_max"], sim_hops=1, budget=max(1, g.n // 100))
+    assert acc > 0
+    heat, st = grass.grass_embed(ctx, dg, torch.as_tensor(P).to(DEV), opts, pass_=1)
+    ref = O.embed(g, P, k=k, t=t, seed=0, pass_=1)
+    say(f"  pcg iters {st['pcg_iters']}, resid64 {st['pcg_resid64']:.2e}")
+    assert st["pcg_resid64"] <= 1e-6
+    _fp32_bar(heat.cpu().numpy().astype(np.float64), ref.heat, P == 0, _cutoff(g, P, ref, 100.0, t))
+    assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
+    assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
+
+
 @pytest.mark.parametrize("hops", [1, 0, -1])
 def test_select_bit_exact_given_scores(ctx, hops):
     g = G.grid2d(48, 40, seed=9)
