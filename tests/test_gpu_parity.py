@@ -231,6 +231,38 @@ def test_c4_sample_tree_and_pcg_pass(ctx, idx):
     assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
 
 
+# every 20th request of the served stream (Barabasi-Albert m = 5, U[0.1,1), k = 16,
+# t = 2, FP32), the first 12 within the oracle's test budget of 25,000 nodes
+C5_SAMPLE = [i for i in range(0, 2000, 20) if G.config_c5_sizes(2000)[i] <= 25000][:12]
+
+
+@pytest.mark.parametrize("idx", C5_SAMPLE)
+def test_c5_sample_tree_and_pcg_pass(ctx, idx):
+    """One request of the served stream, as the server runs it: the tree pass and the
+    first densified pass (the oracle's P; the hubs' long rows and many light
+    children) against the oracle, at the FP32 bar."""
+    g = G.config_c5_graph(int(G.config_c5_sizes(2000)[idx]), seed=idx)
+    say(f"C5 request {idx}", g.n, g.m)
+    k, t = 16, 2
+    tmask = O.max_spanning_tree(g)
+    dg = grass.to_device(g, DEV)
+    opts = grass.make_opts(k=k, t=t, precision=32, seed=0, sigma2=100.0)
+    heat, st = grass.grass_embed(ctx, dg, torch.as_tensor(tmask).to(DEV), opts, pass_=0)
+    r0 = O.embed(g, tmask, k=k, t=t, seed=0)
+    _fp32_bar(heat.cpu().numpy().astype(np.float64), r0.heat, tmask == 0, _cutoff(g, tmask, r0, 100.0, t))
+    assert st["lambda_max"] == pytest.approx(r0.stats["lambda_max"], rel=1e-4)
+    th = O.theta(100.0, r0.stats["lambda_min"], r0.stats["lambda_max"], t)
+    P, acc, _ = O.filter_select(g, r0.heat, tmask, th, r0.stats["heat_max"], sim_hops=1, budget=max(1, g.n // 100))
+    assert acc > 0
+    heat, st = grass.grass_embed(ctx, dg, torch.as_tensor(P).to(DEV), opts, pass_=1)
+    ref = O.embed(g, P, k=k, t=t, seed=0, pass_=1)
+    say(f"  pcg iters {st['pcg_iters']}, resid64 {st['pcg_resid64']:.2e}")
+    assert st["pcg_resid64"] <= 1e-6
+    _fp32_bar(heat.cpu().numpy().astype(np.float64), ref.heat, P == 0, _cutoff(g, P, ref, 100.0, t))
+    assert st["lambda_max"] == pytest.approx(ref.stats["lambda_max"], rel=1e-4)
+    assert st["lambda_min"] == pytest.approx(ref.stats["lambda_min"], rel=1e-12)
+
+
 @pytest.mark.parametrize("hops", [1, 0, -1])
 def test_select_bit_exact_given_scores(ctx, hops):
     g = G.grid2d(48, 40, seed=9)
