@@ -199,8 +199,10 @@ grass_status grass_sparsify_batch(grass_ctx *ctx, int32_t count, const grass_gra
  *     lets the context's autotuner choose per size class (node count in powers of
  *     two, k): it times inner phases with 1, 2, 4 or 8 chunks and with kernel-by-
  *     kernel launches, three phases each, and keeps the fastest.
- * Other k and FP64 run kernel by kernel. Returns GRASS_ERR_INVALID for an unknown
- * mode or chunks_per_read outside 0..64. */
+ * Other k and FP64 run kernel by kernel. A batch reads the mode when it starts and
+ * a server when it is created: call this while no batch call of the context is
+ * running. Returns GRASS_ERR_INVALID for an unknown mode or chunks_per_read
+ * outside 0..64. */
 enum { GRASS_LAUNCH_KERNELS = 0, GRASS_LAUNCH_CAPTURED = 1 };
 grass_status grass_set_launch_mode(grass_ctx *ctx, int32_t mode, int32_t chunks_per_read);
 /* Counters of the block-PCG loops run through the launch schedule above since the
