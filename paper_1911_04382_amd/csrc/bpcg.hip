@@ -21,7 +21,7 @@
 #include "gram.h"
 #include "lap.h"
 #include "profiler.h"
-#include "sched.h"
+#include "launch_sched.h"
 
 #include <chrono>
 #include <climits>

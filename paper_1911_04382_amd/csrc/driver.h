@@ -5,7 +5,7 @@
 
 #include "common.h"
 #include "profiler.h"
-#include "sched.h"
+#include "launch_sched.h"
 
 struct grass_ctx {
     int device = 0;
