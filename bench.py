@@ -450,15 +450,18 @@ def run_partition(args, grass, torch):
 
 
 def run_serving(args, grass, torch):
-    line = serving_leg(args.count, args.c5_max_n, args.rho, args.workers, args.arena_gb, grass, torch)
+    rhos = [float(x) for x in args.rho_sweep.split(",")] if args.rho_sweep else None
+    line = serving_leg(args.count, args.c5_max_n, args.rho, args.workers, args.arena_gb, grass, torch, rhos)
     print(json.dumps(line), flush=True)
 
 
-def serving_leg(count, max_n, rho, workers, arena_gb, grass, torch):
+def serving_leg(count, max_n, rho, workers, arena_gb, grass, torch, rhos=None):
     """C5: a Poisson stream of sparsify requests on preferential-attachment graphs.
     Plain path: one request at a time in arrival order on one stream. Server:
     continuous batching with admission by workspace footprint. Both see the same
-    arrival times; latency = completion - arrival."""
+    arrival times; latency = completion - arrival. With rhos, the server runs once
+    per arrival rate (plain service times measured once) and the line carries every
+    rate under "sweep"."""
     import numpy as np
     from paper_1911_04382_amd import graphs as G
 
@@ -477,59 +480,70 @@ def serving_leg(count, max_n, rho, workers, arena_gb, grass, torch):
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t0)
         log(f"plain path: request {i + 1}/{len(dgs)} (n={dg.n}) {service[-1] * 1e3:.0f} ms")
+    del ws
     mu = 1.0 / (sum(service) / len(service))
-    rate = rho * mu
-    rng = np.random.Generator(np.random.Philox(key=1))
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(dgs)))
-    log(f"C5: {len(dgs)} requests, n in [{min(g.n for g in gs)}, {max(g.n for g in gs)}], mean service "
-        f"{1e3 / mu:.0f} ms, arrival rate {rate:.2f}/s (rho {rho})")
-    # plain FIFO at these arrival times (simulated clock: service times measured above)
-    clock, lat_plain = 0.0, []
-    for a, sv in zip(arrivals, service):
-        clock = max(clock, a) + sv
-        lat_plain.append(clock - a)
-    # the server, live
     need = max(grass.load_library().grass_workspace_bytes(d.n, d.m, opts) for d in dgs)
-    srv = grass.Server(ctx, max(need * workers, int(arena_gb * (1 << 30))), workers=workers)
-    t0 = time.perf_counter()
-    tickets = []
-    seen = [0]
 
-    def progress():  # one line whenever more requests have finished
-        c = sum(1 for t in tickets if srv.poll(t)["state"] in (grass.REQ_DONE, grass.REQ_CANCELLED))
-        if c != seen[0]:
-            seen[0] = c
-            log(f"server: {c}/{len(dgs)} requests finished at t={time.perf_counter() - t0:.1f} s")
+    def run(rho_):
+        rate = rho_ * mu
+        rng = np.random.Generator(np.random.Philox(key=1))
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(dgs)))
+        log(f"C5: {len(dgs)} requests, n in [{min(g.n for g in gs)}, {max(g.n for g in gs)}], mean service "
+            f"{1e3 / mu:.0f} ms, arrival rate {rate:.2f}/s (rho {rho_})")
+        # plain FIFO at these arrival times (simulated clock: service times measured above)
+        clock, lat_plain = 0.0, []
+        for a, sv in zip(arrivals, service):
+            clock = max(clock, a) + sv
+            lat_plain.append(clock - a)
+        # the server, live
+        srv = grass.Server(ctx, max(need * workers, int(arena_gb * (1 << 30))), workers=workers)
+        t0 = time.perf_counter()
+        tickets = []
+        seen = [0]
 
-    for a, dg in zip(arrivals, dgs):
-        while True:
-            dt = t0 + a - time.perf_counter()
-            if dt <= 0:
-                break
-            time.sleep(min(dt, 0.5))
+        def progress():  # one line whenever more requests have finished
+            c = sum(1 for t in tickets if srv.poll(t)["state"] in (grass.REQ_DONE, grass.REQ_CANCELLED))
+            if c != seen[0]:
+                seen[0] = c
+                log(f"server: {c}/{len(dgs)} requests finished at t={time.perf_counter() - t0:.1f} s")
+
+        for a, dg in zip(arrivals, dgs):
+            while True:
+                dt = t0 + a - time.perf_counter()
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.5))
+                progress()
+            tickets.append(srv.submit(dg, opts))
+        while seen[0] < len(dgs):
+            time.sleep(0.5)
             progress()
-        tickets.append(srv.submit(dg, opts))
-    while seen[0] < len(dgs):
-        time.sleep(0.5)
-        progress()
-    srv.wait()
-    infos = [srv.poll(t) for t in tickets]
-    lat_srv = [i["t_end"] - i["t_submit"] for i in infos]
-    ok = all(i["state"] == grass.REQ_DONE and i["status"] >= 0 for i in infos)
-    scored = sum(srv.result(t).summary["scored_edges"] for t in tickets)
-    makespan = max(i["t_end"] for i in infos) - min(i["t_submit"] for i in infos)
-    srv.close()
+        srv.wait()
+        infos = [srv.poll(t) for t in tickets]
+        lat_srv = [i["t_end"] - i["t_submit"] for i in infos]
+        ok = all(i["state"] == grass.REQ_DONE and i["status"] >= 0 for i in infos)
+        scored = sum(srv.result(t).summary["scored_edges"] for t in tickets)
+        makespan = max(i["t_end"] for i in infos) - min(i["t_submit"] for i in infos)
+        srv.close()
+        return {"rho": rho_, "arrival_rate_per_s": rate,
+                "server_ms": {"p50": percentile(lat_srv, 0.5) * 1e3, "p99": percentile(lat_srv, 0.99) * 1e3},
+                "plain_ms": {"p50": percentile(lat_plain, 0.5) * 1e3, "p99": percentile(lat_plain, 0.99) * 1e3},
+                "server_edges_per_s": scored / makespan, "all_done": ok}
+
+    first = run(rho)
+    sweep = [first] + [run(r) for r in (rhos or []) if r != rho] if rhos else None
     line = {"metric": "sparsify latency p50/p99 under a Poisson request stream (server vs plain path)",
-            "value": percentile(lat_srv, 0.99) * 1e3, "unit": "ms (p99, server)", "n_gpus": 1,
+            "value": first["server_ms"]["p99"], "unit": "ms (p99, server)", "n_gpus": 1,
             "higher_is_better": False, "dtype": "f32", "data": "synthetic",
             "config": {"workload": f"C5: {len(dgs)} Barabasi-Albert requests (m=5), n from p(n)~n^-2 on "
                                    f"[1e4, {max_n:.0e}], U[0.1,1), k=16, t=2, sigma^2=100, Poisson arrivals at "
                                    f"rho={rho} of plain capacity",
                        "workers": workers, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
-            "server_ms": {"p50": percentile(lat_srv, 0.5) * 1e3, "p99": percentile(lat_srv, 0.99) * 1e3},
-            "plain_ms": {"p50": percentile(lat_plain, 0.5) * 1e3, "p99": percentile(lat_plain, 0.99) * 1e3},
-            "server_edges_per_s": scored / makespan, "all_done": ok,
-            "mean_service_ms": 1e3 / mu, "arrival_rate_per_s": rate}
+            "server_ms": first["server_ms"], "plain_ms": first["plain_ms"],
+            "server_edges_per_s": first["server_edges_per_s"], "all_done": first["all_done"],
+            "mean_service_ms": 1e3 / mu, "arrival_rate_per_s": first["arrival_rate_per_s"]}
+    if sweep:
+        line["sweep"] = sweep
     ctx.close()
     return line
 
@@ -554,6 +568,7 @@ def main():
                     help="c4: which runs to make (plain = one graph per call; kernels / captured = the batch with "
                          "that launch schedule, captured twice: tuning, then tuned)")
     ap.add_argument("--rho", type=float, default=0.7, help="c5: arrival rate / plain-path capacity")
+    ap.add_argument("--rho-sweep", default="", help="c5: more arrival rates to run after --rho, comma-separated")
     ap.add_argument("--c5-max-n", type=float, default=2e6, help="c5: largest request (nodes)")
     ap.add_argument("--arena-gb", type=float, default=16.0, help="c5: server arena (GiB)")
     ap.add_argument("--serve-count", type=int, default=16,
