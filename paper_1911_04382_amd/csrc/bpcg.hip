@@ -1210,9 +1210,10 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     while (true) {
         bool end = false;
         if (chunks > 0 && can_capture && it + 4 <= pp.max_it) {
-            if (!gh.exec && !capture()) {
+            if (!gh.exec && !capture()) {  // kernel by kernel for the rest of the solve
                 can_capture = false;
                 chunks = 0;
+                cand = -1;  // this phase's timing says nothing about the tuner's candidate
                 continue;
             }
             // up to `chunks` replays, but not past the end that the previous phase's
