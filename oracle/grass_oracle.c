@@ -225,9 +225,9 @@ void orc_tree_solve(int64_t n, const int64_t *parent, const double *pw, const in
  * by preconditioned conjugate gradients, one column at a time, with the grounded
  * tree solve as the preconditioner (the paper solves L_P with AMG; the reading
  * here is PCG with the tree, the same solver class as the GPU path). x0 = 0; stop
- * when ||r||_2 <= rtol ||b||_2 over
- * the non-root rows. Returns the largest iteration count over the columns and
- * writes the largest final relative residual to *resid. */
+ * when ||r||_2 <= rtol ||b||_2 over the non-root rows. Returns the largest
+ * iteration count over the columns and writes the largest final relative
+ * residual to *resid. */
 int orc_pcg(int64_t n, int64_t m, const int32_t *src, const int32_t *dst, const double *w, const uint8_t *inP,
             const int64_t *parent, const double *pw, const int64_t *order, int k, const double *b, double *x,
             double rtol, int maxit, double *resid) {
