@@ -146,8 +146,9 @@ def test_captured_batch_equals_alone(ctx, alone_fused, chunks):
     assert st["iterations"] == sum(r.summary["pcg_iters"] for r in ref)
     assert st["captures"] > 0 and st["graph_replays"] > 0
     if chunks >= 3:
-        # one read per `chunks` replays of four iterations, plus the phase ends
-        assert st["host_reads"] * 4 < st["iterations"] / 2
+        # one read per `chunks` replays of four iterations (fewer near a predicted
+        # phase end): well under the kernel-by-kernel loop's read every 4th iteration
+        assert st["host_reads"] < st["iterations"] // 4
 
 
 def test_kernel_by_kernel_batch_equals_alone(ctx, alone_fused):
