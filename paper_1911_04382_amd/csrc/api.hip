@@ -197,7 +197,7 @@ PassResult run_pass(Session<T> &S, const grass_opts &o, int pass, bool use_pcg, 
         // next product reads it and keeps the right-hand side in FP64
         const bool rhs64 = use_pcg && (step > 1 || !std::is_same<T, double>::value);
         if (rhs64)
-            lap_apply_x64(t, d, v.x64, v.b64, step > 1 ? absmax : nullptr, s);
+            lap_apply_x64(t, d, v.x64, v.b64, step > 1 ? absmax : nullptr, v.eg.lrow, v.eg.nlong, s);
         else
             lap_apply<T>(d, t.rowptr, t.col, v.cval, v.eg, H, Y, -1, step > 1 ? absmax : nullptr, nullptr, s);
         fill_u32(reinterpret_cast<unsigned *>(absmax), 2, 0u, s);

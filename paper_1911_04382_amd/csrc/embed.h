@@ -46,9 +46,11 @@ void lap_long(const Dims &d, const int *rowptr, const int *col, const T *val, co
 // stores beta = -G^-1 Q'x there instead (G^-1 at beta_ginv, both k x k, ld kp).
 // With gate: every kernel of the solve returns at once while *gate is set.
 // y = L_G x64 (grounded nowhere) in FP64, scaled by the power of two from
-// scale_from: the right-hand side of the next L_P solve, kept in FP64.
+// scale_from: the right-hand side of the next L_P solve, kept in FP64. The rows
+// longer than kLongRow (lrow, nlong of them: the long rows of the L_G ELL) take a
+// workgroup each.
 void lap_apply_x64(Topo &t, const Dims &d, const double *x64, double *y, const unsigned long long *scale_from,
-                   hipStream_t s);
+                   const int *lrow, int nlong, hipStream_t s);
 template <typename T>
 void tree_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *y, T *x, const T *rdot, double *dot_part,
                 unsigned long long *absmax, hipStream_t s, const T *qz_q = nullptr, double *qz_part = nullptr,

@@ -229,7 +229,7 @@ __device__ __forceinline__ void sweep_tile(
     __shared__ T s_rw[TN];     // DOWN: 1/parent weight
     // UP, tiles whose nodes have many light children (hubs): the tile's light-child
     // entries go through LDS in rounds of CH, all runs loading at once
-    constexpr int HU = sizeof(T) == 4 ? 8 : 4, CH = RUNS * HU;
+    constexpr int HU = sizeof(T) == 4 ? 16 : 8, CH = RUNS * HU;
     __shared__ T s_ev[UP && HUB ? CH : 1][KP];  // per run: partial sums of its owner segments
     __shared__ int s_eo[UP && HUB ? CH : 1];    // owner (scan index) of each partial
     __shared__ int s_en[UP && HUB ? RUNS : 1];  // partials per run
@@ -1035,11 +1035,55 @@ __global__ __launch_bounds__(kThreads) void k_lap_x64(long long n, int k, const 
     for (int i = g; i < RPB; i += G) {
         long long v = r0 + i;
         if (v >= n) break;
+        const int pb = rowptr[v], pe = rowptr[v + 1];
+        if (pe - pb > kLongRow) continue;  // k_lap_x64_long writes this row
         const double xv = x[v * k + j];
         double acc = 0.0;
-        const int pe = rowptr[v + 1];
-        for (int p = rowptr[v]; p < pe; p++) acc += w[ceid[p]] * (xv - x[(long long)col[p] * k + j]);
+        for (int p = pb; p < pe; p++) acc += w[ceid[p]] * (xv - x[(long long)col[p] * k + j]);
         y[v * k + j] = (TY)(acc * sc);
+    }
+}
+
+// The rows of y = L_G x64 longer than kLongRow entries (list lrow), one workgroup per
+// row: lane groups take every G-th entry, and their FP64 sums are added in group
+// order, so the result does not depend on timing.
+template <int KP>
+__global__ __launch_bounds__(kThreads) void k_lap_x64_long(int k, const int *__restrict__ rowptr,
+                                                           const int *__restrict__ col, const int *__restrict__ ceid,
+                                                           const double *__restrict__ w, const int *__restrict__ lrow,
+                                                           const double *__restrict__ x, double *__restrict__ y,
+                                                           const unsigned long long *__restrict__ scale_from) {
+    constexpr int G = kThreads / KP, U = 4;
+    __shared__ double s[G][KP];
+    const int g = threadIdx.x / KP, j = threadIdx.x % KP;
+    const bool act = j < k;
+    const int v = lrow[blockIdx.x];
+    const int p0 = rowptr[v], p1 = rowptr[v + 1];
+    const double xv = x[act ? (long long)v * k + j : 0];
+    double acc = 0.0;
+    for (int p = p0 + g; p < p1; p += G * U) {
+        int c[U], e[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int q = p + u * G < p1 ? p + u * G : p0;
+            c[u] = col[q];
+            e[u] = ceid[q];
+        }
+        double wv[U], xn[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            wv[u] = w[e[u]];
+            xn[u] = x[act ? (long long)c[u] * k + j : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) acc += p + u * G < p1 ? wv[u] * (xv - xn[u]) : 0.0;
+    }
+    s[g][j] = acc;
+    __syncthreads();
+    if (g == 0 && act) {
+        double t = 0.0;
+        for (int q = 0; q < G; q++) t += s[q][j];
+        y[(long long)v * k + j] = t * pow2_scale(scale_from);
     }
 }
 
@@ -1403,12 +1447,15 @@ void lap_apply(const Dims &d, const int *rowptr, const int *col, const T *val, c
 }
 
 void lap_apply_x64(Topo &t, const Dims &d, const double *x64, double *y, const unsigned long long *scale_from,
-                   hipStream_t s) {
+                   const int *lrow, int nlong, hipStream_t s) {
     const int nbv = vec_blocks(d);
     ProfScope ps(PK_SPMM_G64, 4.0 * (d.n + 1) + 2.0 * d.m * 16 + (double)d.n * d.k * 16, s);
     KP_DISPATCH(d.kp, {
         hipLaunchKernelGGL((k_lap_x64<double, KP>), dim3(xcd_grid(nbv)), dim3(kThreads), 0, s, d.n, d.k, t.rowptr,
                            t.col, t.ceid, t.w, x64, y, scale_from, nbv);
+        if (nlong > 0)
+            hipLaunchKernelGGL(k_lap_x64_long<KP>, dim3(nlong), dim3(kThreads), 0, s, d.k, t.rowptr, t.col, t.ceid,
+                               t.w, lrow, x64, y, scale_from);
     });
     GR_CHECK_LAUNCH();
 }
