@@ -1057,12 +1057,19 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     const Tail<T> tsave = save_tail(v, d);
     SolveInfo info;
     fill_i32(v.tcnt, bpcg_counters(d), 0, s);
-    // r = b - L_P x with x = 0; its norms are the reference of the first inner phase
-    info.resid64 = true_residual<T>(t, v, d, b, s, b64);
-    if (info.resid64 <= pp.rtol) return info;
+    if (pp.single) {
+        // r = b with x = 0 (b grounded by the caller); no FP64 residual
+        hipLaunchKernelGGL(k_copy_vec<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, b, v.r);
+        info.resid64 = -1.0;
+    } else {
+        // r = b - L_P x with x = 0; its norms are the reference of the first inner phase
+        info.resid64 = true_residual<T>(t, v, d, b, s, b64);
+        if (info.resid64 <= pp.rtol) return info;
+    }
     // FP32 working precision: every inner solve runs on an orthonormal basis of the
-    // FP64 residual (FP64 keeps the columns apart by itself)
-    const bool basis = v.z64 != nullptr;
+    // FP64 residual (FP64 keeps the columns apart by itself), unless the caller
+    // turns it off
+    const bool basis = pp.basis && v.z64 != nullptr;
     constexpr bool fp32 = std::is_same<T, float>::value;
     // The loop's decisions are taken on the device (LoopCtl, in the check kernel's
     // tail): iteration count and cap, the end of an inner phase, and in FP32 the stall
@@ -1070,7 +1077,7 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
     // ends there (the FP64 step takes the partial solution) and the rest of the solve
     // normalises its blocks with the dependence threshold kOwnFp32.
     hipLaunchKernelGGL(k_loop_init, dim3(1), dim3(1), 0, s, v.loop, (int)std::min<long long>(pp.max_it, INT_MAX),
-                       fp32 ? 1 : 0);
+                       fp32 && !pp.single ? 1 : 0);
     // a fresh search block: P = Z R^-1 with Z = L_T^+ R and Z'Z = R'R
     auto start_block = [&]() {
         if (basis) rhs_basis<T>(d, v, s);
@@ -1141,6 +1148,27 @@ SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgPar
         });
         GR_CHECK_LAUNCH();
     };
+
+    if (pp.single) {
+        // one inner phase (an inexact L_P solve for a preconditioner): until every
+        // vector's residual has fallen by itol, or max_it; X += P alpha completes it,
+        // and there is no FP64 step
+        long long it = 0;
+        while (true) {
+            it++;
+            first_half(nullptr);
+            if (it >= pp.max_it || (it & 3) == 0) {
+                int lc[2];
+                read_loop(v.loop, lc, s);
+                if (lc[0]) break;
+            }
+            second_half(nullptr);
+        }
+        KP_DISPATCH(d.kp, { launch_rowmul<T, KP, true>(d, v.smallT + T_ALPHA * KK, v.p, v.dx, v.dx, s); });
+        info.iters = it;
+        info.outer = 1;
+        return info;
+    }
 
     // Concurrent paths (LaunchSched of the worker thread): chunks of four iterations
     // captured once per solve as a hipGraph and replayed `chunks` times between host

@@ -69,8 +69,15 @@ struct SolveInfo {
     int outer = 0;
 };
 template <typename T>
+// basis: in FP32, run each inner solve on an orthonormal basis of the FP64 residual
+// (needed when the k right-hand sides can be nearly parallel, as in later power
+// steps; a caller with independent right-hand sides and a fixed short iteration
+// count may leave it off). single: an inexact solve for a preconditioner: one inner
+// phase of the block PCG from x = 0 (until every vector's residual has fallen by
+// max(pcg_inner_rtol, pcg_rtol), or pcg_max_iters) and x = its working-precision
+// solution, with no FP64 outer step or residual (resid64 = -1: not computed).
 SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s,
-                    const double *b64 = nullptr);
+                    const double *b64 = nullptr, bool basis = true, bool single = false);
 
 // r = b - L_P x64 in FP64 (v.r64, and v.r rounded to T), squared norms in
 // red[RED_RN]; returns max_j ||r_j|| / ||b_j|| (b norms in red[RED_BN]).
@@ -103,6 +110,9 @@ void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride
 struct PcgParams {
     double rtol = 1e-6, itol = 1e-2;
     int max_it = 2000, max_repl = 50;
+    bool basis = true;  // FP32: inner solves on an orthonormal basis of the FP64 residual
+    bool single = false;  // one inner phase from x = 0 and x = its solution (no FP64 step);
+                          // the squared norms of b must be in red[RED_RN]
 };
 template <typename T>
 SolveInfo block_pcg(Topo &t, Vecs<T> &v, const Dims &d, const T *b, const PcgParams &pp, hipStream_t s,

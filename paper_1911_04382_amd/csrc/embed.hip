@@ -1615,11 +1615,30 @@ double fcg_outer_step(Topo &t, Vecs<T> &v, const Dims &d, bool first, hipStream_
 
 template <typename T>
 SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const grass_opts &o, hipStream_t s,
-                    const double *b64) {
+                    const double *b64, bool basis, bool single) {
     const long long nk = d.n * d.k;
     const int root = 0;
     const int nbv = vec_blocks(d);
     double *bn = v.red + RED_BN * kMaxK;
+    if (single) {
+        PcgParams pp;
+        pp.rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
+        pp.itol = std::max(o.pcg_inner_rtol > 0 ? o.pcg_inner_rtol : 1e-2, pp.rtol);
+        pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
+        pp.basis = false;
+        pp.single = true;
+        // ||b||^2 per vector: the reference of the phase's convergence test
+        KP_DISPATCH(d.kp, {
+            hipLaunchKernelGGL((k_norm2<T, KP>), dim3(nbv), dim3(kThreads), 0, s, d.n, d.k, b, root, v.part);
+        });
+        GR_CHECK_LAUNCH();
+        col_sum<T>(d, v, v.part, nbv, d.kp, 0, v.red + RED_RN * kMaxK, s);
+        fill_T(v.dx, nk, (T)0, s);
+        SolveInfo info = block_pcg<T>(t, v, d, b, pp, s, nullptr);
+        // x is the working-precision solution itself
+        GR_HIP(hipMemcpyAsync(x, v.dx, nk * sizeof(T), hipMemcpyDeviceToDevice, s));
+        return info;
+    }
     // ||b|| per vector (grounded rows)
     KP_DISPATCH(d.kp, {
         if (b64)
@@ -1638,6 +1657,7 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     pp.itol = std::max(pp.itol, pp.rtol);
     pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
     pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 50;
+    pp.basis = basis;
     SolveInfo info = block_pcg<T>(t, v, d, b, pp, s, b64);
     fill_u32(reinterpret_cast<unsigned *>(v.u64s + U_ABSMAX), 2, 0u, s);
     hipLaunchKernelGGL(k_x64_out<T>, dim3(grid_nk(nk)), dim3(kThreads), 0, s, nk, v.x64, x, v.u64s + U_ABSMAX);
@@ -1724,7 +1744,7 @@ PassScalars finish_estimates(Topo &t, Vecs<T> &v, const Dims &d, hipStream_t s) 
     template double true_residual<T>(Topo &, Vecs<T> &, const Dims &, const T *, hipStream_t, const double *);  \
     template double fcg_outer_step<T>(Topo &, Vecs<T> &, const Dims &, bool, hipStream_t, const double *);        \
     template SolveInfo pcg_solve<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, const grass_opts &,         \
-                                    hipStream_t, const double *);                                                \
+                                    hipStream_t, const double *, bool, bool);                                    \
     template void score_edges<T>(Topo &, Vecs<T> &, const Dims &, const T *, T *, hipStream_t, const double *);  \
     template PassScalars finish_estimates<T>(Topo &, Vecs<T> &, const Dims &, hipStream_t);                      \
     template void absmax_of<T>(const Dims &, const T *, unsigned long long *, hipStream_t);               \

@@ -197,7 +197,9 @@ SddInfo sdd_solve(Topo &t, Vecs<T> &v, const Dims &d, SddVecs<T> &B, const T *b,
         if (tree_only) {
             tree_solve<T>(t, v, d, r, z, nullptr, nullptr, nullptr, s);
         } else {
-            SolveInfo si = pcg_solve<T>(t, v, d, r, z, o, s);
+            // one inner block-PCG phase on the outer iteration's residuals: no
+            // right-hand-side basis, no FP64 step
+            SolveInfo si = pcg_solve<T>(t, v, d, r, z, o, s, nullptr, false, true);
             info.inner += si.iters;
         }
     };
