@@ -297,16 +297,19 @@ grass_status grass_select(grass_ctx *ctx, const grass_graph *g, uint8_t *p_mask,
  * right-hand sides by preconditioned CG, the preconditioner being L_P^+ for the
  * subgraph P of p_mask (device uint8 [m], 1 = spanning-tree edge, 2 = added edge,
  * as grass_sparsify writes it; NULL = the maximum-weight spanning tree alone).
- * L_P^+ is applied exactly (tree solve) when P is a tree, else by the block PCG of
- * the power iterations to opts->pcg_rtol, with flexible CG coefficients. The system
+ * L_P^+ is applied exactly (tree solve) when P is a tree, else inexactly, with
+ * flexible CG coefficients: each application is one working-precision phase of the
+ * power iterations' block PCG from zero, which ends once every column's residual has
+ * fallen by max(opts->pcg_inner_rtol, opts->pcg_rtol) or after opts->pcg_max_iters
+ * iterations (2000 when 0), with no FP64 correction. The system
  * is grounded at node 0 (row and column removed, x[0] = 0); b should sum to zero
  * per column. b, x: device n x k row-major, float32 or float64 per
  * opts->precision, distinct (b is not modified). Stops when every column has
  * ||r|| <= rtol ||b|| for the residual recomputed from x (the recurrence restarts
  * from it, at most 5 times, when working-precision drift leaves it above rtol) or
- * after max_iters outer iterations. opts->pcg_rtol sets the accuracy of each
- * preconditioner solve (1e-2 is enough inside the flexible recurrence; tighter
- * costs inner iterations). info (host, optional):
+ * after max_iters outer iterations. A reduction of 1e-2, or a few iterations, per
+ * application is enough inside the flexible recurrence; tighter costs inner
+ * iterations. info (host, optional):
  * outer iterations (the paper's N), inner block-PCG iterations, the largest
  * ||b - L_G x|| / ||b|| recomputed from x, wall time, edges of P beyond the tree.
  * Returns GRASS_NOT_CONVERGED (x valid) when rtol was not reached. Workspace:
