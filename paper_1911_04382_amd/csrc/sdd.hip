@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kThreads) void k_vec_stats(long long n, const T *__
     s2[threadIdx.x] = b;
     __syncthreads();
     for (int h = kThreads / 2; h >= 1; h >>= 1) {
-        if (threadIdx.x < h) {
+        if ((int)threadIdx.x < h) {
             s1[threadIdx.x] += s1[threadIdx.x + h];
             s2[threadIdx.x] += s2[threadIdx.x + h];
         }
