@@ -155,6 +155,29 @@ def true_kappa(grass, ctx, dg, mask, cfg, steps=(50, 100)):
     return out
 
 
+def lambda_leg(grass, ctx, dg, cfg, torch, ws, steps=8):
+    """The benchmark workload with lambda_max estimated from `steps` continued power
+    steps (Sec. IV-C.1; the paper's Table IV uses fewer than ten) instead of the
+    t-step iterate that also scores the edges: one timed call, and the true kappa
+    of its sparsifier (50 continued steps on one vector, FP64)."""
+    c = dict(cfg)
+    c["lambda_steps"] = steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        r = grass.grass_sparsify(ctx, dg, grass.make_opts(**c), ws=ws)
+    except grass.GrassError as e:
+        return {"lambda_steps": steps, "error": str(e)}
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    s = r.summary
+    out = {"lambda_steps": steps, "status": r.status, "seconds": dt, "passes": s["passes"],
+           "added_edges": s["added_edges"], "scored_edges": s["scored_edges"],
+           "edges_per_s": s["scored_edges"] / dt, "kappa_est": s["kappa"], "pcg_iters": s["pcg_iters"]}
+    out["true_kappa_50_steps"] = true_kappa(grass, ctx, dg, r.mask, cfg, steps=(50,))["kappa_upper"]
+    return out
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
     """A plain device-to-device copy of known size (the PMC byte counters of this
     kernel calibrate FETCH_SIZE / WRITE_SIZE against real bytes)."""
@@ -718,6 +741,9 @@ def main():
         line["true_kappa"] = true_kappa(grass, ctx, dg, r.mask, cfg)
         line["true_kappa"]["kappa_est_t"] = summaries[-1]["kappa"]
         log(f"  {line['true_kappa']}")
+        log("the same workload with lambda_max from 8 continued power steps ...")
+        line["lambda_steps_8"] = lambda_leg(grass, ctx, dg, cfg, torch, ws)
+        log(f"  {line['lambda_steps_8']}")
         log(f"served-stream leg: {args.serve_count} C5 requests ...")
         sv = serving_leg(args.serve_count, 2e6, args.rho, args.workers, args.arena_gb, grass, torch)
         line["serving"] = {"workload": sv["config"]["workload"], "workers": sv["config"]["workers"],

@@ -95,7 +95,7 @@ typedef struct {
     int32_t lambda_steps;   /* power steps for lambda_max (>= t continues the vectors) [0 = t] */
     double pcg_rtol;        /* relative residual target of every L_P solve, checked in FP64 [1e-6] */
     int32_t pcg_max_iters;  /* working-precision block-PCG iterations per L_P solve, all inner solves
-                               together [2000] */
+                               together [8000] */
     double pcg_inner_rtol;  /* residual reduction of each inner block-PCG solve between the FP64
                                flexible-CG steps around it [1e-2] */
     int32_t pcg_max_outer;  /* FP64 flexible-CG steps per L_P solve [50] */
@@ -301,7 +301,7 @@ grass_status grass_select(grass_ctx *ctx, const grass_graph *g, uint8_t *p_mask,
  * flexible CG coefficients: each application is one working-precision phase of the
  * power iterations' block PCG from zero, which ends once every column's residual has
  * fallen by max(opts->pcg_inner_rtol, opts->pcg_rtol) or after opts->pcg_max_iters
- * iterations (2000 when 0), with no FP64 correction. The system
+ * iterations (8000 when 0), with no FP64 correction. The system
  * is grounded at node 0 (row and column removed, x[0] = 0); b should sum to zero
  * per column. b, x: device n x k row-major, float32 or float64 per
  * opts->precision, distinct (b is not modified). Stops when every column has

@@ -571,7 +571,7 @@ grass_opts grass_opts_default(void) {
     o.sim_hops = 1;
     o.lambda_steps = 0;
     o.pcg_rtol = 1e-6;
-    o.pcg_max_iters = 2000;
+    o.pcg_max_iters = 8000;
     o.pcg_inner_rtol = 1e-2;
     o.pcg_max_outer = 50;
     o.precision = 32;

@@ -109,7 +109,7 @@ void col_sum(const Dims &d, Vecs<T> &v, const double *part, int nblk, int stride
 // x64 and dx hold zero and red[RED_BN] the squared norms of b on entry.
 struct PcgParams {
     double rtol = 1e-6, itol = 1e-2;
-    int max_it = 2000, max_repl = 50;
+    int max_it = 8000, max_repl = 50;
     bool basis = true;  // FP32: inner solves on an orthonormal basis of the FP64 residual
     bool single = false;  // one inner phase from x = 0 and x = its solution (no FP64 step);
                           // the squared norms of b must be in red[RED_RN]

@@ -1624,7 +1624,7 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
         PcgParams pp;
         pp.rtol = o.pcg_rtol > 0 ? o.pcg_rtol : 1e-6;
         pp.itol = std::max(o.pcg_inner_rtol > 0 ? o.pcg_inner_rtol : 1e-2, pp.rtol);
-        pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
+        pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 8000;
         pp.basis = false;
         pp.single = true;
         // ||b||^2 per vector: the reference of the phase's convergence test
@@ -1655,7 +1655,7 @@ SolveInfo pcg_solve(Topo &t, Vecs<T> &v, const Dims &d, const T *b, T *x, const 
     pp.itol = o.pcg_inner_rtol > 0 ? o.pcg_inner_rtol : 1e-2;
     // a target looser than the inner phase's reduction ends that phase at the target
     pp.itol = std::max(pp.itol, pp.rtol);
-    pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 2000;
+    pp.max_it = o.pcg_max_iters > 0 ? o.pcg_max_iters : 8000;
     pp.max_repl = o.pcg_max_outer > 0 ? o.pcg_max_outer : 50;
     pp.basis = basis;
     SolveInfo info = block_pcg<T>(t, v, d, b, pp, s, b64);
