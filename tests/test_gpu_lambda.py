@@ -69,3 +69,30 @@ def test_lambda_steps_parity_and_accuracy(ctx, idx, steps):
     heat0, _ = grass.grass_embed(ctx, dg, pm, grass.make_opts(k=8, t=2, precision=64, seed=1, pcg_rtol=1e-12),
                                  pass_=0)
     assert torch.equal(heat, heat0)
+
+
+def test_fp32_sparsify_with_eight_step_lambda(ctx):
+    """FP32 sparsify of a 40^3 mesh of the benchmark's family (weights 10^U(-3,3),
+    k = 32, t = 2) with lambda_max from 8 continued power steps: every L_P solve
+    reaches pcg_rtol although the continued vectors grow nearly parallel, the loop
+    stops at kappa_est <= sigma^2, and the 8-step estimate of the final pass is
+    close to the sparsifier's lambda_max continued to 100 steps on one vector in
+    FP64 (a Rayleigh quotient: at most that value, and the paper reports errors of
+    a few percent with fewer than ten steps)."""
+    g = G.config_c2(40)
+    print("lambda_steps = 8 sparsify:", g.n, g.m, flush=True)
+    dg = grass.to_device(g, DEV)
+    sigma2 = 100.0
+    r = grass.grass_sparsify(ctx, dg, grass.make_opts(k=32, t=2, sigma2=sigma2, precision=32, seed=1,
+                                                       lambda_steps=8))
+    print(f"  {r.summary['passes']} passes, kappa_est {r.summary['kappa']:.2f}", flush=True)
+    assert r.status == grass.OK
+    assert all(t["pcg_resid64"] <= 1e-6 for t in r.trace[1:])
+    assert all(t["flags"] == 0 for t in r.trace)
+    assert r.summary["kappa"] <= sigma2
+    _, st = grass.grass_embed(ctx, dg, r.mask, grass.make_opts(k=1, t=2, lambda_steps=100, precision=64, seed=1),
+                              pass_=1000)
+    est, ref = r.summary["lambda_max"], st["lambda_max"]
+    print(f"  lambda_max: 8-step estimate {est:.3f}, 100 steps {ref:.3f}", flush=True)
+    assert est <= ref * (1 + 1e-3)
+    assert est >= 0.9 * ref
