@@ -35,6 +35,23 @@ def test_opts_defaults():
     assert o.pcg_rtol == 1e-6 and o.init_mask is None
 
 
+def test_opts_defaults_match_the_header():
+    """Every bracketed default in the grass_opts declaration of include/grass.h is
+    the value grass_opts_default() returns."""
+    import re
+
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "grass.h")).read()
+    body = hdr[hdr.index("/* Options (grass_opts_default()"):hdr.index("} grass_opts;")]
+    fields = re.findall(r"\b(?:double|int32_t|uint64_t)\s+(\w+);\s*/\*(.*?)\*/", body, re.S)
+    assert len(fields) >= 12
+    o = grass.load_library().grass_opts_default()
+    for name, doc in fields:
+        m = re.search(r"\[([^\]=]+?)(?:\s*=.*)?\]", doc)
+        assert m, f"{name}: no default in brackets"
+        want = float(m.group(1))
+        assert float(getattr(o, name)) == want, f"{name}: header says {want}, library returns {getattr(o, name)}"
+
+
 def test_workspace_bytes_monotone_and_rejects_bad_sizes():
     lib = grass.load_library()
     o = lib.grass_opts_default()
