@@ -120,6 +120,9 @@ EMBED_CASES = [
     # hubs: rows of L_G beyond the long-row bound, tree nodes with dozens of light children
     ("ba_hubs_k16", lambda: G.ba(12000, seed=5), 16, 2, 32),
     ("rgg_k5", lambda: G.rgg(2500, seed=7), 5, 2, 32),
+    # the widest block (k = 64, the largest k the library takes) and a single vector
+    ("mesh_k64", lambda: G.mesh3d(10, 9, 8, weights=(G.W_LOGUNIFORM10, -3, 3), seed=2), 64, 2, 32),
+    ("grid_k1_fp64", lambda: G.grid2d(30, 30, seed=8), 1, 2, 64),
 ]
 
 
@@ -159,6 +162,8 @@ PCG_CASES = [
     ("mesh_fp32_k32", lambda: G.mesh3d(18, 16, 15, weights=(G.W_LOGUNIFORM10, -3, 3), seed=6), 32, 32),
     # hubs: L_P rows past the long-row bound (their tails summed by a workgroup each)
     ("ba_hubs_fp32", lambda: G.ba(12000, seed=5), 16, 32),
+    # k = 64: the widest block PCG (no MFMA kernels at this width)
+    ("mesh_fp32_k64", lambda: G.mesh3d(12, 11, 10, weights=(G.W_LOGUNIFORM10, -3, 3), seed=7), 64, 32),
 ]
 
 
