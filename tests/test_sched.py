@@ -1,5 +1,6 @@
 """Host logic of the launch schedule's autotuner (csrc/launch_sched.h, plain C++): built with
-g++ into a small program that feeds it timings and prints its choices."""
+g++ (with the address and undefined-behaviour sanitizers) into a small program that feeds
+it timings and prints its choices."""
 import os
 import shutil
 import subprocess
@@ -45,7 +46,10 @@ def test_tuner_explores_every_candidate_then_keeps_the_fastest(tmp_path):
     src = tmp_path / "tuner.cpp"
     exe = tmp_path / "tuner"
     src.write_text(PROGRAM)
-    subprocess.check_call(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)])
+    # address and undefined-behaviour sanitizers on the host-only tuner code
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-I", CSRC, str(src), "-o",
+                           str(exe)])
     out = subprocess.check_output([str(exe)], text=True).split("\n")
     assert out[0] == "keys 1 1 1"
     samples = out[1].split()[1:]
