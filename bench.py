@@ -519,7 +519,9 @@ def serving_leg(count, max_n, rho, workers, arena_gb, grass, torch, rhos=None):
             clock = max(clock, a) + sv
             lat_plain.append(clock - a)
         # the server, live
+        free0 = torch.cuda.mem_get_info()[0]
         srv = grass.Server(ctx, max(need * workers, int(arena_gb * (1 << 30))), workers=workers)
+        hbm_server = free0 - torch.cuda.mem_get_info()[0]  # the server's arena and per-worker state
         t0 = time.perf_counter()
         tickets = []
         seen = [0]
@@ -551,7 +553,8 @@ def serving_leg(count, max_n, rho, workers, arena_gb, grass, torch, rhos=None):
         return {"rho": rho_, "arrival_rate_per_s": rate,
                 "server_ms": {"p50": percentile(lat_srv, 0.5) * 1e3, "p99": percentile(lat_srv, 0.99) * 1e3},
                 "plain_ms": {"p50": percentile(lat_plain, 0.5) * 1e3, "p99": percentile(lat_plain, 0.99) * 1e3},
-                "server_edges_per_s": scored / makespan, "all_done": ok}
+                "server_edges_per_s": scored / makespan, "server_requests_per_s": len(dgs) / makespan,
+                "hbm_server_bytes": int(hbm_server), "all_done": ok}
 
     first = run(rho)
     sweep = [first] + [run(r) for r in (rhos or []) if r != rho] if rhos else None
@@ -563,7 +566,9 @@ def serving_leg(count, max_n, rho, workers, arena_gb, grass, torch, rhos=None):
                                    f"rho={rho} of plain capacity",
                        "workers": workers, "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")},
             "server_ms": first["server_ms"], "plain_ms": first["plain_ms"],
-            "server_edges_per_s": first["server_edges_per_s"], "all_done": first["all_done"],
+            "server_edges_per_s": first["server_edges_per_s"],
+            "server_requests_per_s": first["server_requests_per_s"],
+            "hbm_server_bytes": first["hbm_server_bytes"], "all_done": first["all_done"],
             "mean_service_ms": 1e3 / mu, "arrival_rate_per_s": first["arrival_rate_per_s"]}
     if sweep:
         line["sweep"] = sweep
@@ -748,7 +753,9 @@ def main():
         sv = serving_leg(args.serve_count, 2e6, args.rho, args.workers, args.arena_gb, grass, torch)
         line["serving"] = {"workload": sv["config"]["workload"], "workers": sv["config"]["workers"],
                            "server_ms": sv["server_ms"], "plain_ms": sv["plain_ms"],
-                           "server_edges_per_s": sv["server_edges_per_s"], "all_done": sv["all_done"],
+                           "server_edges_per_s": sv["server_edges_per_s"],
+                           "server_requests_per_s": sv["server_requests_per_s"],
+                           "hbm_server_bytes": sv["hbm_server_bytes"], "all_done": sv["all_done"],
                            "mean_service_ms": sv["mean_service_ms"], "arrival_rate_per_s": sv["arrival_rate_per_s"],
                            "plain_latency": "simulated from measured one-at-a-time service times at the same "
                                             "arrival times"}
