@@ -178,6 +178,26 @@ def lambda_leg(grass, ctx, dg, cfg, torch, ws, steps=8):
     return out
 
 
+def copy_ceiling(torch, nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """This device's measured HBM ceiling: a plain device-to-device copy of nbytes,
+    timed with events over reps copies after one untimed one; GB/s counts the bytes
+    read and the bytes written."""
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2.0 * n * 4 / sec / 1e9
+
+
 def copy_calibration(nbytes: int = 1 << 30, reps: int = 5):
     """A plain device-to-device copy of known size (the PMC byte counters of this
     kernel calibrate FETCH_SIZE / WRITE_SIZE against real bytes)."""
@@ -707,6 +727,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.workload),
                 "traffic_unit": "bytes per launch", "avg_launch_us": avg_s * 1e6,
                 "launches": p["launches"], "alg_bytes_per_launch": p["alg_bytes"] / p["launches"]}
+        ceil = copy_ceiling(torch)
+        roof.update(copy_ceiling_GBs=ceil, frac_of_copy_ceiling=achieved / ceil)
     line = {
         "metric": METRIC,
         "value": value,
